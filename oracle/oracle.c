@@ -1,0 +1,263 @@
+/*
+ * oracle.c -- plain, slow, CPU reference for semiring matrix multiplication
+ * and Strassen's algorithm, written from the paper "Balanced Partitioning of
+ * Several Cache-Oblivious Algorithms" (Tang & Gao).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library calls this code.  Only the
+ * test suite, the smoke check and the benchmark's CPU-baseline leg load it.
+ * It shares no source, header, table or helper with the GPU library.
+ *
+ * What it computes (section "PACO MM", problem statement): C = A (x) B over a
+ * closed semiring (S, (+), (x), 0, 1) with A n-by-k, B k-by-m, C n-by-m; every
+ * matrix is row-major with an explicit leading dimension.  Each entry is the
+ * plain definition, an ascending-l fold
+ *
+ *     C[i][j] = 0  (+)  A[i][0] (x) B[0][j]  (+)  ...  (+)  A[i][k-1] (x) B[k-1][j]
+ *
+ * with no blocking, no reordering and no partitioning.  The PACO partition does
+ * not change this value for the integer semirings, and changes only rounding
+ * for the (+,x) ring.  When `accumulate` is set the fold starts from the old
+ * C[i][j] instead of 0, which gives C <- C (+) A (x) B (the experiments section
+ * computes C = C + A x B).  k = 0 leaves the empty fold: 0, or the old C.
+ *
+ * The paper does not fix the semiring constants.  The readings used here:
+ *   (min,+) int32: 0 = INF = 2^30, (x) is the saturating add min(a+b, INF),
+ *                  domain {0 .. 2^30}.  Arithmetic in int64, so a+b cannot
+ *                  overflow.
+ *   (max,+) int32: 0 = NEG_INF = -2^30, (x) is a+b when both are finite and
+ *                  NEG_INF when either is NEG_INF (NEG_INF absorbs), finite
+ *                  domain [-2^28, 2^28].  Arithmetic in int64.
+ *   boolean:       (+) = OR, (x) = AND, 0 = false.
+ *   (+,x) ring:    IEEE binary64 for every product and sum (products of two
+ *                  binary32 values are exact in binary64).
+ *
+ * Strassen (section "PACO Strassen"): the seven products of the 1-based
+ * formulas S1..S7, T1..T7, M_r = S_r (x) T_r and the four quadrant sums of C,
+ * applied recursively for a given number of levels and finished by the
+ * classic triple loop.
+ *
+ * Loops over i may run under OpenMP; each C[i][j] is still one sequential fold.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+#define OR_INF ((int64_t)1 << 30)
+#define OR_NEG_INF (-((int64_t)1 << 30))
+
+/* ---------------------------------------------------------------- (min,+) */
+static int64_t minplus_mul(int64_t a, int64_t b) {
+  int64_t s = a + b;
+  return s < OR_INF ? s : OR_INF;
+}
+
+void oracle_minplus(int64_t n, int64_t m, int64_t k,
+                    const int32_t* A, int64_t lda,
+                    const int32_t* B, int64_t ldb,
+                    int32_t* C, int64_t ldc, int accumulate) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = 0; j < m; ++j) {
+      int64_t acc = accumulate ? (int64_t)C[i * ldc + j] : OR_INF;
+      for (int64_t l = 0; l < k; ++l) {
+        int64_t t = minplus_mul(A[i * lda + l], B[l * ldb + j]);
+        if (t < acc) acc = t;
+      }
+      C[i * ldc + j] = (int32_t)acc;
+    }
+  }
+}
+
+/* ---------------------------------------------------------------- (max,+) */
+static int64_t maxplus_mul(int64_t a, int64_t b) {
+  if (a == OR_NEG_INF || b == OR_NEG_INF) return OR_NEG_INF;
+  return a + b;
+}
+
+void oracle_maxplus(int64_t n, int64_t m, int64_t k,
+                    const int32_t* A, int64_t lda,
+                    const int32_t* B, int64_t ldb,
+                    int32_t* C, int64_t ldc, int accumulate) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = 0; j < m; ++j) {
+      int64_t acc = accumulate ? (int64_t)C[i * ldc + j] : OR_NEG_INF;
+      for (int64_t l = 0; l < k; ++l) {
+        int64_t t = maxplus_mul(A[i * lda + l], B[l * ldb + j]);
+        if (t > acc) acc = t;
+      }
+      C[i * ldc + j] = (int32_t)acc;
+    }
+  }
+}
+
+/* ---------------------------------------------------------------- boolean */
+/* Bit-by-bit definition on unpacked 0/1 bytes. */
+void oracle_bool_bits(int64_t n, int64_t m, int64_t k,
+                      const uint8_t* A, const uint8_t* B, uint8_t* C,
+                      int accumulate) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = 0; j < m; ++j) {
+      int acc = accumulate ? (C[i * m + j] != 0) : 0;
+      for (int64_t l = 0; l < k; ++l)
+        acc = acc | ((A[i * k + l] != 0) & (B[l * m + j] != 0));
+      C[i * m + j] = (uint8_t)acc;
+    }
+  }
+}
+
+/* Packed layout: row r of an R-by-W bit matrix is ceil(W/32) uint32 words,
+ * bit w of the row is bit (w % 32) of word (w / 32), least significant first.
+ * Row-OR form of the same definition: row i of C is the OR of the rows l of B
+ * for which bit l of row i of A is set.  Padding bits of C are written 0. */
+void oracle_bool_packed(int64_t n, int64_t m, int64_t k,
+                        const uint32_t* A, const uint32_t* B, uint32_t* C,
+                        int accumulate) {
+  int64_t kw = (k + 31) / 32, mw = (m + 31) / 32;
+  uint32_t last_mask = (m % 32) ? ((1u << (m % 32)) - 1u) : 0xffffffffu;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n; ++i) {
+    uint32_t* c = C + i * mw;
+    if (!accumulate)
+      for (int64_t w = 0; w < mw; ++w) c[w] = 0;
+    for (int64_t l = 0; l < k; ++l) {
+      if ((A[i * kw + l / 32] >> (l % 32)) & 1u) {
+        const uint32_t* b = B + l * mw;
+        for (int64_t w = 0; w < mw; ++w) c[w] |= b[w];
+      }
+    }
+    if (mw > 0) c[mw - 1] &= last_mask;
+  }
+}
+
+/* ---------------------------------------------------------------- ring */
+/* C64[i][j] = sum_l A[i][l]*B[l][j] in binary64, ascending l; when absC is
+ * not NULL it also receives sum_l |A[i][l]|*|B[l][j]| (the scale used for
+ * the componentwise error bound).  Only the `nrows` rows listed in `rows`
+ * are computed (rows == NULL means all n rows); output row r of C64 is input
+ * row rows[r]. */
+void oracle_ring_f64(int64_t n, int64_t m, int64_t k,
+                     const float* A, int64_t lda,
+                     const float* B, int64_t ldb,
+                     const int64_t* rows, int64_t nrows,
+                     double* C64, double* absC) {
+  if (rows == NULL) nrows = n;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t r = 0; r < nrows; ++r) {
+    int64_t i = rows ? rows[r] : r;
+    for (int64_t j = 0; j < m; ++j) {
+      double acc = 0.0, aacc = 0.0;
+      for (int64_t l = 0; l < k; ++l) {
+        double p = (double)A[i * lda + l] * (double)B[l * ldb + j];
+        acc += p;
+        aacc += fabs(p);
+      }
+      C64[r * m + j] = acc;
+      if (absC) absC[r * m + j] = aacc;
+    }
+  }
+}
+
+/* Same fold on binary64 operands (used by the Strassen oracle's leaves and
+ * by callers holding binary64 data). */
+void oracle_ring_f64_dd(int64_t n, int64_t m, int64_t k,
+                        const double* A, int64_t lda,
+                        const double* B, int64_t ldb,
+                        double* C, int64_t ldc) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < m; ++j) {
+      double acc = 0.0;
+      for (int64_t l = 0; l < k; ++l) acc += A[i * lda + l] * B[l * ldb + j];
+      C[i * ldc + j] = acc;
+    }
+}
+
+void oracle_ring_i64(int64_t n, int64_t m, int64_t k,
+                     const int64_t* A, int64_t lda,
+                     const int64_t* B, int64_t ldb,
+                     int64_t* C, int64_t ldc) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < m; ++j) {
+      int64_t acc = 0;
+      for (int64_t l = 0; l < k; ++l) acc += A[i * lda + l] * B[l * ldb + j];
+      C[i * ldc + j] = acc;
+    }
+}
+
+/* ---------------------------------------------------------------- Strassen */
+/* One level of Strassen on an h-by-h quadrant split of n-by-n matrices
+ * (n = 2h), written once for binary64 and once for int64 through a macro of
+ * the element type.  Quadrant X_ab of a matrix X with leading dimension ld
+ * starts at X + a*h*ld + b*h.  The level uses the 1-based formulas:
+ *   S1 = A00+A11  S2 = A10+A11  S3 = A00      S4 = A11
+ *   S5 = A00+A01  S6 = A10-A00  S7 = A01-A11
+ *   T1 = B00+B11  T2 = B00      T3 = B01-B11  T4 = B10-B00
+ *   T5 = B11      T6 = B00+B01  T7 = B10+B11
+ *   M_r = S_r T_r
+ *   C00 = M1+M4-M5+M7   C01 = M3+M5   C10 = M2+M4   C11 = M1+M3-M2+M6
+ */
+#define DEFINE_STRASSEN(NAME, T, LEAF)                                          \
+  static void NAME##_add(int64_t h, const T* X, int64_t ldx, int sx,            \
+                         const T* Y, int64_t ldy, int sy, T* Z) {               \
+    for (int64_t i = 0; i < h; ++i)                                             \
+      for (int64_t j = 0; j < h; ++j) {                                         \
+        T v = 0;                                                                \
+        if (sx) v = (sx > 0) ? X[i * ldx + j] : -X[i * ldx + j];                \
+        if (sy) v = (sy > 0) ? v + Y[i * ldy + j] : v - Y[i * ldy + j];         \
+        Z[i * h + j] = v;                                                       \
+      }                                                                         \
+  }                                                                             \
+  static void NAME##_rec(int64_t n, const T* A, int64_t lda, const T* B,        \
+                         int64_t ldb, T* C, int64_t ldc, int levels) {          \
+    if (levels <= 0 || n % 2 != 0) {                                            \
+      LEAF(n, n, n, A, lda, B, ldb, C, ldc);                                    \
+      return;                                                                   \
+    }                                                                           \
+    int64_t h = n / 2;                                                          \
+    const T *A00 = A, *A01 = A + h, *A10 = A + h * lda, *A11 = A + h * lda + h; \
+    const T *B00 = B, *B01 = B + h, *B10 = B + h * ldb, *B11 = B + h * ldb + h; \
+    T* buf = (T*)malloc(sizeof(T) * (size_t)(h * h) * 9);                       \
+    T *S = buf, *Tm = buf + h * h, *M = buf + 2 * h * h;                        \
+    /* S_r, T_r as (first operand, sign, second operand, sign). */              \
+    const T* sa[7] = {A00, A10, A00, A11, A00, A10, A01};                       \
+    const T* sb[7] = {A11, A11, A00, A11, A01, A00, A11};                       \
+    int ss[7][2] = {{1, 1}, {1, 1}, {1, 0}, {1, 0}, {1, 1}, {1, -1}, {1, -1}};  \
+    const T* ta[7] = {B00, B00, B01, B10, B11, B00, B10};                       \
+    const T* tb[7] = {B11, B00, B11, B00, B11, B01, B11};                       \
+    int ts[7][2] = {{1, 1}, {1, 0}, {1, -1}, {1, -1}, {1, 0}, {1, 1}, {1, 1}};  \
+    for (int r = 0; r < 7; ++r) {                                               \
+      NAME##_add(h, sa[r], lda, ss[r][0], sb[r], lda, ss[r][1], S);             \
+      NAME##_add(h, ta[r], ldb, ts[r][0], tb[r], ldb, ts[r][1], Tm);            \
+      NAME##_rec(h, S, h, Tm, h, M + r * h * h, h, levels - 1);                 \
+    }                                                                           \
+    const T *M1 = M, *M2 = M + h * h, *M3 = M + 2 * h * h, *M4 = M + 3 * h * h; \
+    const T *M5 = M + 4 * h * h, *M6 = M + 5 * h * h, *M7 = M + 6 * h * h;      \
+    for (int64_t i = 0; i < h; ++i)                                             \
+      for (int64_t j = 0; j < h; ++j) {                                         \
+        int64_t e = i * h + j;                                                  \
+        C[i * ldc + j] = M1[e] + M4[e] - M5[e] + M7[e];                         \
+        C[i * ldc + h + j] = M3[e] + M5[e];                                     \
+        C[(h + i) * ldc + j] = M2[e] + M4[e];                                   \
+        C[(h + i) * ldc + h + j] = M1[e] + M3[e] - M2[e] + M6[e];               \
+      }                                                                         \
+    free(buf);                                                                  \
+  }
+
+DEFINE_STRASSEN(strassen_f64, double, oracle_ring_f64_dd)
+DEFINE_STRASSEN(strassen_i64, int64_t, oracle_ring_i64)
+
+/* C = A B for n-by-n row-major matrices through `levels` Strassen levels
+ * (fewer if n stops being even), classic triple loop below. */
+void oracle_strassen_f64(int64_t n, const double* A, const double* B,
+                         double* C, int levels) {
+  strassen_f64_rec(n, A, n, B, n, C, n, levels);
+}
+
+void oracle_strassen_i64(int64_t n, const int64_t* A, const int64_t* B,
+                         int64_t* C, int levels) {
+  strassen_i64_rec(n, A, n, B, n, C, n, levels);
+}
