@@ -1,0 +1,211 @@
+/*
+ * paco.h -- C ABI of libpaco: PACO-partitioned semiring matrix multiplication
+ * and Strassen's algorithm on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Tang & Gao, "Balanced Partitioning of Several Cache-Oblivious
+ * Algorithms" (arXiv 2011.01441), sections "PACO MM" (problem statement,
+ * cuboid view, MM-1-Piece), "Extension to Heterogeneous Computing System"
+ * and "PACO Strassen".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are dense and row-major.  A is n-by-k, B is k-by-m, C is
+ *    n-by-m (the problem statement's orientation), each with a leading
+ *    dimension (elements between rows) of at least its column count.
+ *  - Operand and result pointers A, B, C are DEVICE pointers owned by the
+ *    caller.  The library never frees them and keeps no reference past the
+ *    call.  Calls are asynchronous on the context's stream: keep the buffers
+ *    alive and unmodified until that stream has been synchronised.
+ *  - Boolean matrices are bit-packed: row r of an R-by-W bit matrix is
+ *    ceil(W/32) uint32 words, bit w lives in bit (w % 32) of word (w / 32),
+ *    least significant bit first; padding bits of inputs must be 0 and
+ *    padding bits of C are written 0.  Leading dimensions count words.
+ *  - Semiring constants (the paper leaves them open; these are this
+ *    library's definitions):
+ *      (min,+) int32: zero INF = 2^30; product min(a+b, INF); valid entries
+ *                     lie in [0, 2^30].
+ *      (max,+) int32: zero NEG_INF = -2^30; product a+b, or NEG_INF when
+ *                     either factor is NEG_INF; finite entries lie in
+ *                     [-2^28, 2^28].
+ *      boolean      : OR of ANDs.
+ *      (+,x) float32: IEEE float32 results; see paco_precision.
+ *    Entries outside these domains give unspecified (but memory-safe)
+ *    results.
+ *  - Errors are returned as paco_status; nothing aborts or throws across
+ *    the ABI.  A per-context message is kept for the last failure.
+ *  - One context per host thread.  Workspace (temporary faces for k-cuts,
+ *    Strassen temporaries, piece descriptors) is owned by the context,
+ *    grows on demand and is capped by the budget given at creation.
+ */
+#ifndef PACO_H
+#define PACO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum paco_status {
+  PACO_OK = 0,
+  PACO_ERR_INVALID_ARG = 1,   /* null pointer, negative size, bad enum, bad ld */
+  PACO_ERR_UNSUPPORTED = 2,   /* e.g. Strassen on a non-ring semiring */
+  PACO_ERR_OUT_OF_MEMORY = 3, /* a device allocation failed */
+  PACO_ERR_BUDGET = 4,        /* workspace or admission budget exceeded */
+  PACO_ERR_HIP = 5,           /* a HIP runtime call failed */
+  PACO_ERR_INTERNAL = 6,
+  PACO_ERR_NOT_FOUND = 7      /* unknown server ticket */
+} paco_status;
+
+typedef enum paco_semiring {
+  PACO_SR_PLUS_TIMES_F32 = 0, /* (+,x) ring on float32 */
+  PACO_SR_MIN_PLUS_I32 = 1,   /* tropical (min,+) on int32 */
+  PACO_SR_MAX_PLUS_I32 = 2,   /* (max,+) on int32 */
+  PACO_SR_OR_AND_B1 = 3       /* boolean, bit-packed uint32 words */
+} paco_semiring;
+
+/* Arithmetic of the (+,x) ring path.
+ *  FP32   : float32 matrix-core products with float32 accumulation.
+ *  BF16X3 : each float32 operand x is split into hi = bf16(x) and
+ *           lo = bf16(x - hi) (round to nearest even); the product is
+ *           hi*hi' + hi*lo' + lo*hi' on bf16 matrix cores with float32
+ *           accumulation (split-precision method of Henry, Tang & Heinecke,
+ *           2019).
+ *  BF16X6 : three-way split hi, mid, lo and the six products whose
+ *           combined significance reaches float32 (hi*hi', hi*mid',
+ *           mid*hi', mid*mid', hi*lo', lo*hi').
+ *  AUTO   : BF16X3 when its predicted componentwise error at this k is at
+ *           most 2^-21, BF16X6 otherwise.
+ * Integer and boolean semirings ignore this field. */
+typedef enum paco_precision {
+  PACO_PREC_FP32 = 0,
+  PACO_PREC_BF16X3 = 1,
+  PACO_PREC_BF16X6 = 2,
+  PACO_PREC_AUTO = 3
+} paco_precision;
+
+/* How the n-by-m-by-k iteration cuboid is split over workgroups.
+ *  PACO : MM-1-Piece (section "PACO MM", corollary mm-1-piece): recursive
+ *         cuts of the longest dimension of a same-sized virtual cuboid in
+ *         the ratio floor(p/2):ceil(p/2), one cuboid per processor (one
+ *         persistent workgroup per compute unit).
+ *  GRID : the baseline the paper's experiments compare against in spirit:
+ *         the same microkernel on a plain grid of output tiles with a
+ *         split-k factor chosen by the autotuner. */
+typedef enum paco_part_mode { PACO_PART_PACO = 0, PACO_PART_GRID = 1 } paco_part_mode;
+
+typedef struct paco_ctx_s* paco_ctx;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  workspace_budget_bytes caps the
+ * device workspace the context may hold (0 = 64 GiB).  The context creates
+ * no stream of its own; it launches on the stream set by paco_set_stream
+ * (initially the null stream). */
+paco_status paco_create(paco_ctx* out, int device, uint64_t workspace_budget_bytes);
+paco_status paco_destroy(paco_ctx ctx);
+/* `stream` is a hipStream_t passed as an opaque pointer. */
+paco_status paco_set_stream(paco_ctx ctx, void* stream);
+/* Number of processors p used by default: the device's compute units. */
+int paco_num_cus(paco_ctx ctx);
+const char* paco_status_string(paco_status s);
+const char* paco_last_error(paco_ctx ctx);
+
+/* --------------------------------------------------------- semiring MM */
+
+/* C = A (x) B over semiring `sr` (section "PACO MM", problem statement),
+ * dense operands with lda = k, ldb = m, ldc = m (words for boolean),
+ * PACO partition over all compute units, precision AUTO for the ring.
+ * n = 0 or m = 0 is a no-op; k = 0 writes the semiring zero into C. */
+paco_status paco_semiring_mm(paco_ctx ctx, int64_t n, int64_t m, int64_t k,
+                             paco_semiring sr, const void* A, const void* B, void* C);
+
+typedef struct paco_mm_desc {
+  int64_t n, m, k;
+  paco_semiring sr;
+  const void* A; int64_t lda;   /* 0 = dense default */
+  const void* B; int64_t ldb;
+  void* C;       int64_t ldc;
+  int32_t accumulate;           /* nonzero: C <- C (+) A (x) B */
+  paco_precision precision;     /* ring only */
+  paco_part_mode part;
+  int32_t p;                    /* processors (workgroups); 0 = compute units */
+  int32_t grid_split_k;         /* GRID mode split-k; 0 = autotuned */
+  int32_t verify_rows;          /* >0: float64 check of this many sampled
+                                   rows on the GPU (ring only); the call
+                                   then synchronises the stream */
+  uint64_t verify_seed;
+} paco_mm_desc;
+
+typedef struct paco_mm_result {
+  paco_precision precision;     /* precision actually used (ring) */
+  int32_t p;                    /* processors used */
+  int32_t n_pieces;             /* non-empty pieces */
+  int64_t max_piece_volume, min_piece_volume;  /* n'*m'*k' over non-empty pieces */
+  int64_t temp_elems;           /* temporary-face elements for k-cuts */
+  int32_t n_kcuts;              /* pieces writing a temporary face */
+  double verify_max_rel;        /* max |C-C64| / (|A||B|) over sampled rows, -1 if not verified */
+  double verify_max_abs;        /* max |C-C64| over sampled rows */
+} paco_mm_result;
+
+/* Extended form: explicit leading dimensions, accumulation, precision,
+ * partition mode and processor count.  `out` may be NULL. */
+paco_status paco_semiring_mm_ex(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* out);
+
+/* ------------------------------------------------------------- Strassen */
+
+/* C = A B for n-by-n float32 matrices (section "PACO Strassen"): `levels`
+ * levels of Strassen's 7-product recursion (1-based S1..S7, T1..T7,
+ * M_r = S_r T_r, quadrant sums of M), all 7^levels leaf products run as one
+ * PACO-partitioned batch on the ring kernel at precision `leaf`.
+ * levels in [0, 3]; n must be divisible by 2^levels (else UNSUPPORTED).
+ * A, B, C dense (ld = n), device pointers. */
+paco_status paco_strassen_mm(paco_ctx ctx, int64_t n, const float* A, const float* B,
+                             float* C, int levels, paco_precision leaf);
+
+/* ----------------------------------------------------- float64 checker */
+
+/* For `nrows` rows listed in the device array `rows` (int64), compute on
+ * the GPU in float64 C64 = A B and S = |A||B| and reduce
+ *   out[0] = max |C - C64| / S   (componentwise, entries with S = 0 skipped)
+ *   out[1] = max |C - C64|
+ *   out[2] = sum (C - C64)^2,  out[3] = sum C64^2
+ * into the host array out[4].  Dense float32 A (n-by-k), B (k-by-m),
+ * C (n-by-m).  Synchronises the context stream. */
+paco_status paco_verify_rows_f64(paco_ctx ctx, int64_t n, int64_t m, int64_t k,
+                                 const float* A, const float* B, const float* C,
+                                 const int64_t* rows, int64_t nrows, double* out);
+
+/* ------------------------------------------------------------ partition */
+
+typedef struct paco_piece {
+  int64_t n0, n1, m0, m1, k0, k1;  /* half-open ranges of the cuboid */
+  int32_t proc;                    /* processor it is assigned to */
+  int32_t temp;                    /* 1: writes a temporary face (k0 > 0) */
+  int32_t round;                   /* assignment round (multi-piece mode),
+                                      0 for MM-1-Piece */
+  int32_t depth;                   /* number of cuts from the root cuboid */
+} paco_piece;
+
+typedef struct paco_part_opts {
+  int32_t p;                 /* processors, >= 1 */
+  int32_t q_n, q_m, q_k;     /* cut quanta (cuts land on multiples); 0 = 1 */
+  const double* weights;     /* NULL: equal processors; else p throughputs,
+                                cuts split in the ratio of the two halves'
+                                summed throughput (heterogeneous variant) */
+  int32_t multi_piece;       /* 1: PACO MM pruned-BFS multi-piece mode */
+} paco_part_opts;
+
+/* Host-only.  Partition the n-by-m-by-k cuboid over opts->p processors.
+ * Writes at most `cap` pieces to `out` and the total count to *n_out
+ * (call with cap = 0 to size the array).  MM-1-Piece gives exactly p pieces
+ * (possibly empty ones for tiny problems); multi-piece mode gives the
+ * pruned-BFS assignment of section "PACO MM". */
+paco_status paco_partition(int64_t n, int64_t m, int64_t k, const paco_part_opts* opts,
+                           paco_piece* out, int64_t cap, int64_t* n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PACO_H */

@@ -1,0 +1,243 @@
+"""Python binding of libpaco: PACO-partitioned semiring matrix multiplication
+and Strassen's algorithm on one MI355X.
+
+Argument marshalling only: every step runs in the HIP kernels of libpaco.so.
+PyTorch provides device memory and the current stream.  `torch` is imported
+before the library is loaded so that libpaco binds to the HIP runtime torch
+has already loaded (both carry the soname libamdhip64.so.7).
+"""
+import ctypes
+import os
+
+import torch
+
+__all__ = ["Context", "PacoError", "semiring_mm", "strassen_mm", "partition", "lib",
+           "SEMIRING", "PRECISION", "INF", "NEG_INF", "library_path"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libpaco.so")
+
+INF = 1 << 30
+NEG_INF = -(1 << 30)
+SEMIRING = {"ring": 0, "plus_times": 0, "minplus": 1, "maxplus": 2, "bool": 3}
+PRECISION = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "auto": 3}
+PRECISION_NAME = {v: k for k, v in PRECISION.items()}
+PART = {"paco": 0, "grid": 1}
+_DTYPE = {0: torch.float32, 1: torch.int32, 2: torch.int32, 3: torch.int32}
+
+
+class PacoError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libpaco status {status}: {msg}")
+        self.status = status
+
+
+class MMDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("sr", ctypes.c_int),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64),
+                ("accumulate", ctypes.c_int32), ("precision", ctypes.c_int),
+                ("part", ctypes.c_int), ("p", ctypes.c_int32),
+                ("grid_split_k", ctypes.c_int32), ("verify_rows", ctypes.c_int32),
+                ("verify_seed", ctypes.c_uint64)]
+
+
+class MMResult(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("p", ctypes.c_int32), ("n_pieces", ctypes.c_int32),
+                ("max_piece_volume", ctypes.c_int64), ("min_piece_volume", ctypes.c_int64),
+                ("temp_elems", ctypes.c_int64), ("n_kcuts", ctypes.c_int32),
+                ("verify_max_rel", ctypes.c_double), ("verify_max_abs", ctypes.c_double)]
+
+
+class Piece(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int64), ("n1", ctypes.c_int64), ("m0", ctypes.c_int64),
+                ("m1", ctypes.c_int64), ("k0", ctypes.c_int64), ("k1", ctypes.c_int64),
+                ("proc", ctypes.c_int32), ("temp", ctypes.c_int32),
+                ("round", ctypes.c_int32), ("depth", ctypes.c_int32)]
+
+
+class PartOpts(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("q_n", ctypes.c_int32), ("q_m", ctypes.c_int32),
+                ("q_k", ctypes.c_int32), ("weights", ctypes.POINTER(ctypes.c_double)),
+                ("multi_piece", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpaco.so; raises if it has not been built (no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(library_path):
+        raise ImportError(f"{library_path} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(library_path)
+    vp, i64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    L.paco_create.argtypes = [ctypes.POINTER(vp), ci, ctypes.c_uint64]
+    L.paco_destroy.argtypes = [vp]
+    L.paco_set_stream.argtypes = [vp, vp]
+    L.paco_num_cus.argtypes = [vp]
+    L.paco_num_cus.restype = ci
+    L.paco_status_string.argtypes = [ci]
+    L.paco_status_string.restype = ctypes.c_char_p
+    L.paco_last_error.argtypes = [vp]
+    L.paco_last_error.restype = ctypes.c_char_p
+    L.paco_semiring_mm.argtypes = [vp, i64, i64, i64, ci, vp, vp, vp]
+    L.paco_semiring_mm_ex.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(MMResult)]
+    L.paco_strassen_mm.argtypes = [vp, i64, vp, vp, vp, ci, ci]
+    L.paco_verify_rows_f64.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, i64,
+                                       ctypes.POINTER(ctypes.c_double)]
+    L.paco_partition.argtypes = [i64, i64, i64, ctypes.POINTER(PartOpts), ctypes.POINTER(Piece),
+                                 i64, ctypes.POINTER(i64)]
+    for name in ("paco_create", "paco_destroy", "paco_set_stream", "paco_semiring_mm",
+                 "paco_semiring_mm_ex", "paco_strassen_mm", "paco_verify_rows_f64",
+                 "paco_partition"):
+        getattr(L, name).restype = ci
+    _lib = L
+    return L
+
+
+def _check(st, ctx=None):
+    if st != 0:
+        L = lib()
+        msg = L.paco_last_error(ctx).decode() if ctx else ""
+        raise PacoError(st, f"{L.paco_status_string(st).decode()}: {msg}")
+
+
+def partition(n, m, k, p, q=(1, 1, 1), weights=None, multi_piece=False):
+    """Host-only PACO partition (MM-1-Piece, or pruned-BFS multi-piece):
+    a list of dicts with n0,n1,m0,m1,k0,k1, proc, temp, round, depth."""
+    L = lib()
+    o = PartOpts(p, q[0], q[1], q[2], None, 1 if multi_piece else 0)
+    if weights is not None:
+        arr = (ctypes.c_double * p)(*[float(w) for w in weights])
+        o.weights = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+    cnt = ctypes.c_int64(0)
+    _check(L.paco_partition(n, m, k, ctypes.byref(o), None, 0, ctypes.byref(cnt)))
+    buf = (Piece * max(cnt.value, 1))()
+    _check(L.paco_partition(n, m, k, ctypes.byref(o), buf, cnt.value, ctypes.byref(cnt)))
+    names = [f[0] for f in Piece._fields_]
+    return [{f: getattr(buf[i], f) for f in names} for i in range(cnt.value)]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+class Context:
+    """A libpaco context on one device; launches on torch's current stream."""
+
+    def __init__(self, device=0, workspace_budget=0):
+        self._L = lib()
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(self._L.paco_create(ctypes.byref(h), device, workspace_budget))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.paco_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_cus(self):
+        return self._L.paco_num_cus(self._h)
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _check(self._L.paco_set_stream(self._h, ctypes.c_void_p(s)), self._h)
+
+    def _check_tensor(self, t, name, dtype):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.device.index != self.device:
+            raise ValueError(f"{name} must be a tensor on cuda:{self.device}")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+        if t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError(f"{name} must be 2-D with unit column stride")
+
+    def semiring_mm(self, A, B, semiring="ring", *, n=None, m=None, k=None, C=None,
+                    accumulate=False, precision="auto", part="paco", p=0, split_k=0,
+                    verify_rows=0, verify_seed=0, return_result=False):
+        """C = A (x) B.  Boolean operands are bit-packed int32 words; pass
+        their logical sizes n, m, k.  Returns C (and a result dict)."""
+        sr = SEMIRING[semiring]
+        dt = _DTYPE[sr]
+        self._check_tensor(A, "A", dt)
+        self._check_tensor(B, "B", dt)
+        if sr == 3:
+            if n is None or m is None or k is None:
+                raise ValueError("boolean operands need explicit n, m, k (bits)")
+            mw = (m + 31) // 32
+        else:
+            n, k = A.shape
+            k2, m = B.shape
+            if k2 != k:
+                raise ValueError(f"inner sizes differ: {A.shape} x {B.shape}")
+            mw = m
+        if C is None:
+            C = torch.empty((n, mw), dtype=dt, device=A.device)
+        else:
+            self._check_tensor(C, "C", dt)
+        d = MMDesc(n, m, k, sr, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C), C.stride(0),
+                   1 if accumulate else 0, PRECISION[precision], PART[part], p, split_k,
+                   verify_rows, verify_seed)
+        r = MMResult()
+        self._stream()
+        _check(self._L.paco_semiring_mm_ex(self._h, ctypes.byref(d), ctypes.byref(r)), self._h)
+        if not return_result:
+            return C
+        res = {f[0]: getattr(r, f[0]) for f in MMResult._fields_}
+        res["precision"] = PRECISION_NAME.get(res["precision"], res["precision"])
+        return C, res
+
+    def strassen_mm(self, A, B, levels=2, leaf="bf16x3", C=None):
+        self._check_tensor(A, "A", torch.float32)
+        self._check_tensor(B, "B", torch.float32)
+        n = A.shape[0]
+        if A.shape != (n, n) or B.shape != (n, n) or not A.is_contiguous() or not B.is_contiguous():
+            raise ValueError("Strassen needs dense square operands of equal size")
+        if C is None:
+            C = torch.empty((n, n), dtype=torch.float32, device=A.device)
+        self._stream()
+        _check(self._L.paco_strassen_mm(self._h, n, _ptr(A), _ptr(B), _ptr(C), levels,
+                                        PRECISION[leaf]), self._h)
+        return C
+
+    def verify_rows(self, A, B, C, rows):
+        """float64 check of the listed rows: (max rel, max abs, sum sq diff, sum sq ref)."""
+        n, k = A.shape
+        m = B.shape[1]
+        rows = rows.to(device=A.device, dtype=torch.int64).contiguous()
+        out = (ctypes.c_double * 4)()
+        self._stream()
+        _check(self._L.paco_verify_rows_f64(self._h, n, m, k, _ptr(A), _ptr(B), _ptr(C),
+                                            _ptr(rows), rows.numel(), out), self._h)
+        return tuple(out)
+
+
+_default = None
+
+
+def _ctx():
+    global _default
+    if _default is None:
+        _default = Context(torch.cuda.current_device())
+    return _default
+
+
+def semiring_mm(A, B, semiring="ring", **kw):
+    return _ctx().semiring_mm(A, B, semiring, **kw)
+
+
+def strassen_mm(A, B, levels=2, leaf="bf16x3"):
+    return _ctx().strassen_mm(A, B, levels, leaf)

@@ -1,0 +1,406 @@
+// api.cpp -- the C ABI of libpaco (include/paco.h): contexts, plan cache,
+// workspace, and the semiring MM entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/paco.h"
+#include "ctx.h"
+#include "kernels.h"
+#include "partition.h"
+#include "plan.h"
+
+using namespace paco;
+
+namespace paco {
+
+void set_err(paco_ctx ctx, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+}
+
+paco_status hip_fail(paco_ctx ctx, hipError_t e, const char* what) {
+  set_err(ctx, std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? PACO_ERR_OUT_OF_MEMORY : PACO_ERR_HIP;
+}
+
+DevPlan::~DevPlan() {
+  if (d_items) (void)hipFree(d_items);
+  if (d_wg_off) (void)hipFree(d_wg_off);
+  if (d_tiles) (void)hipFree(d_tiles);
+  if (d_srcs) (void)hipFree(d_srcs);
+}
+
+template <class T>
+static hipError_t upload(T** dst, const std::vector<T>& v) {
+  *dst = nullptr;
+  if (v.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void**)dst, sizeof(T) * v.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice);
+}
+
+paco_status upload_plan(paco_ctx ctx, DevPlan* dp) {
+  hipError_t e;
+  if ((e = upload(&dp->d_items, dp->h.items)) != hipSuccess) return hip_fail(ctx, e, "plan upload");
+  if ((e = upload(&dp->d_wg_off, dp->h.wg_off)) != hipSuccess) return hip_fail(ctx, e, "plan upload");
+  if ((e = upload(&dp->d_tiles, dp->h.tiles)) != hipSuccess) return hip_fail(ctx, e, "plan upload");
+  if ((e = upload(&dp->d_srcs, dp->h.srcs)) != hipSuccess) return hip_fail(ctx, e, "plan upload");
+  return PACO_OK;
+}
+
+paco_status ensure_ws(paco_ctx ctx, uint64_t bytes) {
+  if (bytes <= ctx->ws_bytes) return PACO_OK;
+  if (bytes > ctx->budget) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "workspace of %llu bytes exceeds the budget of %llu bytes",
+             (unsigned long long)bytes, (unsigned long long)ctx->budget);
+    set_err(ctx, buf);
+    return PACO_ERR_BUDGET;
+  }
+  hipError_t e;
+  if (ctx->ws) {
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_fail(ctx, e, "workspace sync");
+    (void)hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  // round up to 64 MiB so small growth steps do not reallocate every call
+  uint64_t want = (bytes + (64ull << 20) - 1) & ~((64ull << 20) - 1);
+  if (want > ctx->budget) want = bytes;
+  if ((e = hipMalloc(&ctx->ws, want)) != hipSuccess) return hip_fail(ctx, e, "workspace alloc");
+  ctx->ws_bytes = want;
+  return PACO_OK;
+}
+
+int choose_int_tile(const std::vector<Piece>& pcs) {
+  // critical-path padded work of each tile shape, small tiles weighted by
+  // their lower efficiency
+  const int cand[4] = {INT_T128x128, INT_T256x64, INT_T64x128, INT_T64x64};
+  const double eff[4] = {1.0, 1.0, 1.15, 1.35};
+  int best = INT_T128x128;
+  double bestc = 1e300;
+  for (int c = 0; c < 4; ++c) {
+    IntTileShape ts = int_tile_shape(cand[c]);
+    double worst = 0;
+    for (const Piece& p : pcs) {
+      if (p.empty()) continue;
+      double tiles = (double)((p.n1 - p.n0 + ts.tm - 1) / ts.tm) * (double)((p.m1 - p.m0 + ts.tn - 1) / ts.tn);
+      worst = std::max(worst, tiles * ts.tm * ts.tn * (double)(p.k1 - p.k0) * eff[c]);
+    }
+    if (worst < bestc) {
+      bestc = worst;
+      best = cand[c];
+    }
+  }
+  return best;
+}
+
+}  // namespace paco
+
+// ------------------------------------------------------------------ context
+
+extern "C" paco_status paco_create(paco_ctx* out, int device, uint64_t budget) {
+  if (!out) return PACO_ERR_INVALID_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return PACO_ERR_HIP;
+  if (device < 0 || device >= ndev) return PACO_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return PACO_ERR_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return PACO_ERR_HIP;
+  auto* c = new paco_ctx_s();
+  c->device = device;
+  c->num_cus = prop.multiProcessorCount;
+  c->budget = budget ? budget : (64ull << 30);
+  *out = c;
+  return PACO_OK;
+}
+
+extern "C" paco_status paco_destroy(paco_ctx ctx) {
+  if (!ctx) return PACO_ERR_INVALID_ARG;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->plans.clear();
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->d_verify) (void)hipFree(ctx->d_verify);
+  destroy_ctx_extras(ctx);
+  delete ctx;
+  return PACO_OK;
+}
+
+extern "C" paco_status paco_set_stream(paco_ctx ctx, void* stream) {
+  if (!ctx) return PACO_ERR_INVALID_ARG;
+  ctx->stream = (hipStream_t)stream;
+  return PACO_OK;
+}
+
+extern "C" int paco_num_cus(paco_ctx ctx) { return ctx ? ctx->num_cus : 0; }
+
+extern "C" const char* paco_status_string(paco_status s) {
+  switch (s) {
+    case PACO_OK: return "ok";
+    case PACO_ERR_INVALID_ARG: return "invalid argument";
+    case PACO_ERR_UNSUPPORTED: return "unsupported";
+    case PACO_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case PACO_ERR_BUDGET: return "budget exceeded";
+    case PACO_ERR_HIP: return "HIP runtime error";
+    case PACO_ERR_INTERNAL: return "internal error";
+    case PACO_ERR_NOT_FOUND: return "not found";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* paco_last_error(paco_ctx ctx) {
+  return ctx ? ctx->last_error.c_str() : "null context";
+}
+
+// --------------------------------------------------------------- partition
+
+extern "C" paco_status paco_partition(int64_t n, int64_t m, int64_t k, const paco_part_opts* o,
+                                      paco_piece* out, int64_t cap, int64_t* n_out) {
+  if (!o || !n_out || n < 0 || m < 0 || k < 0 || o->p < 1 || o->p > (1 << 20)) return PACO_ERR_INVALID_ARG;
+  if (cap > 0 && !out) return PACO_ERR_INVALID_ARG;
+  PartOpts po;
+  po.p = o->p;
+  po.q[0] = o->q_n > 0 ? o->q_n : 1;
+  po.q[1] = o->q_m > 0 ? o->q_m : 1;
+  po.q[2] = o->q_k > 0 ? o->q_k : 1;
+  po.weights = o->weights;
+  if (o->weights)
+    for (int i = 0; i < o->p; ++i)
+      if (!(o->weights[i] > 0) || !std::isfinite(o->weights[i])) return PACO_ERR_INVALID_ARG;
+  std::vector<Piece> pcs = o->multi_piece ? partition_multi(n, m, k, po) : partition_mm1(n, m, k, po);
+  *n_out = (int64_t)pcs.size();
+  for (int64_t i = 0; i < std::min<int64_t>(cap, (int64_t)pcs.size()); ++i) {
+    const Piece& p = pcs[i];
+    out[i].n0 = p.n0; out[i].n1 = p.n1;
+    out[i].m0 = p.m0; out[i].m1 = p.m1;
+    out[i].k0 = p.k0; out[i].k1 = p.k1;
+    out[i].proc = p.proc;
+    out[i].temp = (!p.empty() && p.k0 > 0) ? 1 : 0;
+    out[i].round = p.round;
+    out[i].depth = p.depth;
+  }
+  return PACO_OK;
+}
+
+// -------------------------------------------------------------- semiring MM
+
+namespace {
+
+struct Norm {  // normalised call
+  paco_semiring sr;
+  int64_t n, m, k;           // logical sizes
+  int64_t mu, ku;            // kernel units of m and k-words (bool: words)
+  int64_t lda, ldb, ldc;     // kernel units
+  int prec;
+};
+
+int64_t words(int64_t bits) { return (bits + 31) / 32; }
+
+// Float32 componentwise-error model of bf16x3 at depth k (see paco.h, AUTO).
+int auto_precision(int64_t k) {
+  // measured/emulated max normalised error of bf16x3 falls like 1/sqrt(k):
+  // about 2^-17.2 at k = 32 and 2^-20 at k = 1024; bf16x3 is chosen when the
+  // predicted value is at most 2^-21, i.e. k >= 4096.
+  return k >= 4096 ? PREC_BF16X3 : PREC_BF16X6;
+}
+
+}  // namespace
+
+paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res);
+
+extern "C" paco_status paco_semiring_mm(paco_ctx ctx, int64_t n, int64_t m, int64_t k,
+                                        paco_semiring sr, const void* A, const void* B, void* C) {
+  paco_mm_desc d;
+  memset(&d, 0, sizeof d);
+  d.n = n; d.m = m; d.k = k; d.sr = sr;
+  d.A = A; d.B = B; d.C = C;
+  d.precision = PACO_PREC_AUTO;
+  d.part = PACO_PART_PACO;
+  return paco_semiring_mm_ex(ctx, &d, nullptr);
+}
+
+extern "C" paco_status paco_semiring_mm_ex(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
+  if (!ctx) return PACO_ERR_INVALID_ARG;
+  if (!d) {
+    set_err(ctx, "null descriptor");
+    return PACO_ERR_INVALID_ARG;
+  }
+  return run_mm(ctx, d, res);
+}
+
+paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
+  if (res) {
+    memset(res, 0, sizeof *res);
+    res->verify_max_rel = -1;
+    res->verify_max_abs = -1;
+  }
+  if (d->sr < PACO_SR_PLUS_TIMES_F32 || d->sr > PACO_SR_OR_AND_B1) {
+    set_err(ctx, "unknown semiring");
+    return PACO_ERR_INVALID_ARG;
+  }
+  if (d->n < 0 || d->m < 0 || d->k < 0 || d->n >= (1ll << 31) || d->m >= (1ll << 31) ||
+      d->k >= (1ll << 31)) {
+    set_err(ctx, "sizes must lie in [0, 2^31)");
+    return PACO_ERR_INVALID_ARG;
+  }
+  if (d->precision < PACO_PREC_FP32 || d->precision > PACO_PREC_AUTO || d->part < PACO_PART_PACO ||
+      d->part > PACO_PART_GRID || d->p < 0 || d->grid_split_k < 0 || d->verify_rows < 0) {
+    set_err(ctx, "invalid option");
+    return PACO_ERR_INVALID_ARG;
+  }
+  const bool is_bool = d->sr == PACO_SR_OR_AND_B1;
+  Norm z;
+  z.sr = d->sr;
+  z.n = d->n; z.m = d->m; z.k = d->k;
+  z.mu = is_bool ? words(d->m) : d->m;
+  z.ku = is_bool ? words(d->k) : d->k;
+  z.lda = d->lda ? d->lda : z.ku;
+  z.ldb = d->ldb ? d->ldb : z.mu;
+  z.ldc = d->ldc ? d->ldc : z.mu;
+  if (z.lda < z.ku || z.ldb < z.mu || z.ldc < z.mu) {
+    set_err(ctx, "leading dimension smaller than the row length");
+    return PACO_ERR_INVALID_ARG;
+  }
+  if (z.lda >= (1ll << 22) || z.ldb >= (1ll << 22)) {
+    set_err(ctx, "leading dimensions of A and B must be below 2^22 elements");
+    return PACO_ERR_UNSUPPORTED;
+  }
+  if (d->verify_rows > 0 && d->sr != PACO_SR_PLUS_TIMES_F32) {
+    set_err(ctx, "verify_rows applies to the ring only");
+    return PACO_ERR_INVALID_ARG;
+  }
+  if (z.n == 0 || z.m == 0) return PACO_OK;
+  if (!d->C || (z.k > 0 && (!d->A || !d->B))) {
+    set_err(ctx, "null operand");
+    return PACO_ERR_INVALID_ARG;
+  }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  if (z.k == 0) {
+    if (d->accumulate) return PACO_OK;
+    e = launch_fill_zero(is_bool ? SR_BOOL : (int)d->sr, d->C, z.n, z.mu, z.ldc, ctx->stream);
+    return e == hipSuccess ? PACO_OK : hip_fail(ctx, e, "fill");
+  }
+  z.prec = -1;
+  if (d->sr == PACO_SR_PLUS_TIMES_F32) {
+    if (d->precision == PACO_PREC_AUTO) z.prec = auto_precision(z.k);
+    else z.prec = (int)d->precision;
+  }
+  const int p = d->p > 0 ? d->p : ctx->num_cus;
+  if (p > 65536) {
+    set_err(ctx, "p above 65536");
+    return PACO_ERR_INVALID_ARG;
+  }
+
+  // ---- plan
+  char key[256];
+  snprintf(key, sizeof key, "mm/%d/%lld/%lld/%lld/%d/%d/%d/%d", (int)d->sr, (long long)z.n,
+           (long long)z.m, (long long)z.k, (int)d->part, p, d->grid_split_k, z.prec);
+  DevPlan* dp = nullptr;
+  auto itp = ctx->plans.find(key);
+  if (itp != ctx->plans.end()) {
+    dp = itp->second.get();
+  } else {
+    std::unique_ptr<DevPlan> np(new DevPlan());
+    int fam = d->sr == PACO_SR_PLUS_TIMES_F32 ? 2 : (is_bool ? 1 : 0);
+    std::vector<Piece> pcs;
+    int tile = 0, tm = 0, tn = 0, bk = 32;
+    if (d->part == PACO_PART_PACO) {
+      PartOpts po;
+      po.p = p;
+      if (fam == 1) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
+      else if (fam == 2) { po.q[0] = 16; po.q[1] = 16; po.q[2] = 32; }
+      pcs = partition_mm1(z.n, z.m, z.k, po);
+      if (fam == 1) {  // bits -> words in m
+        for (Piece& pc : pcs) { pc.m0 /= 32; pc.m1 = words(pc.m1); }
+      }
+      if (fam == 0) tile = choose_int_tile(pcs);
+      else if (fam == 1) tile = choose_bool_tile(pcs);
+      else tile = choose_ring_tile(pcs, z.prec);
+    } else {
+      if (fam == 0) {
+        tile = z.m <= 64 ? INT_T256x64 : INT_T128x128;
+        IntTileShape ts = int_tile_shape(tile);
+        tm = ts.tm; tn = ts.tn;
+      } else if (fam == 1) {
+        tile = BOOL_T128x128W;
+        BoolTileShape ts = bool_tile_shape(tile);
+        tm = ts.tm; tn = ts.tnw * 32;
+      } else {
+        tile = RING_T128x128;
+        RingTileShape ts = ring_tile_shape(tile, z.prec);
+        tm = ts.tm; tn = ts.tn; bk = ts.bk;
+      }
+      int64_t tiles = ((z.n + tm - 1) / tm) * ((z.m + tn - 1) / tn);
+      int64_t kb = (z.k + bk - 1) / bk;
+      int sk = d->grid_split_k;
+      if (sk <= 0) sk = (int)std::max<int64_t>(1, std::min<int64_t>(kb, (ctx->num_cus + tiles - 1) / tiles));
+      pcs = partition_grid(z.n, z.m, z.k, tm, tn, bk, sk);
+      if (fam == 1)
+        for (Piece& pc : pcs) { pc.m0 /= 32; pc.m1 = words(pc.m1); }
+    }
+    std::vector<TaggedPiece> tp(pcs.size());
+    for (size_t i = 0; i < pcs.size(); ++i) tp[i] = {pcs[i], 0, d->part == PACO_PART_PACO ? pcs[i].proc : (int)i};
+    int nwg = d->part == PACO_PART_PACO ? p : (int)pcs.size();
+    std::vector<ProbGeom> geom{{z.n, z.mu, z.ku}};
+    np->h = build_plan(tp, nwg, d->part == PACO_PART_PACO, geom);
+    np->tile = tile;
+    np->fam = fam;
+    np->p = p;
+    paco_status st = upload_plan(ctx, np.get());
+    if (st != PACO_OK) return st;
+    dp = np.get();
+    ctx->plans[key] = std::move(np);
+  }
+
+  // ---- workspace
+  paco_status st = ensure_ws(ctx, (uint64_t)dp->h.temp_elems * 4);
+  if (st != PACO_OK) return st;
+
+  // ---- launch
+  ProbRef pr;
+  memset(&pr, 0, sizeof pr);
+  pr.base.A = d->A; pr.base.B = d->B; pr.base.C = d->C;
+  pr.base.lda = z.lda; pr.base.ldb = z.ldb; pr.base.ldc = z.ldc;
+  pr.base.n = (int32_t)z.n; pr.base.m = (int32_t)z.m; pr.base.k = (int32_t)z.k;
+  pr.base.accumulate = d->accumulate ? 1 : 0;
+  if (dp->fam == 0)
+    e = launch_semiring_int((int)d->sr, dp->tile, pr, dp->d_items, dp->d_wg_off, dp->h.nwg,
+                            dp->h.xcd_remap, ctx->ws, ctx->stream);
+  else if (dp->fam == 1)
+    e = launch_semiring_bool(dp->tile, pr, dp->d_items, dp->d_wg_off, dp->h.nwg, dp->h.xcd_remap,
+                             ctx->ws, ctx->stream);
+  else
+    e = launch_ring(z.prec, dp->tile, pr, dp->d_items, dp->d_wg_off, dp->h.nwg, dp->h.xcd_remap,
+                    ctx->ws, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "semiring kernel launch");
+  if (!dp->h.tiles.empty()) {
+    e = launch_reduce(is_bool ? SR_BOOL : (int)d->sr, pr, dp->d_tiles, (int)dp->h.tiles.size(),
+                      dp->d_srcs, ctx->ws, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
+  }
+  if (res) {
+    res->precision = (paco_precision)(z.prec < 0 ? PACO_PREC_FP32 : z.prec);
+    res->p = d->part == PACO_PART_PACO ? p : dp->h.nwg;
+    res->n_pieces = dp->h.n_pieces;
+    res->max_piece_volume = dp->h.vmax;
+    res->min_piece_volume = dp->h.vmin;
+    res->temp_elems = dp->h.temp_elems;
+    res->n_kcuts = dp->h.n_kcuts;
+  }
+  if (d->verify_rows > 0) {
+    st = verify_sampled(ctx, z.n, z.m, z.k, (const float*)d->A, z.lda, (const float*)d->B, z.ldb,
+                        (const float*)d->C, z.ldc, d->verify_rows, d->verify_seed, res);
+    if (st != PACO_OK) return st;
+  }
+  return PACO_OK;
+}

@@ -1,0 +1,61 @@
+// ctx.h -- internal state of a libpaco context.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/paco.h"
+#include "partition.h"
+#include "plan.h"
+
+namespace paco {
+
+// A cached plan: host work lists and their device copies.
+struct DevPlan {
+  HostPlan h;
+  int tile = 0;
+  int fam = 0;  // 0 integer VALU, 1 boolean, 2 ring
+  int p = 0;
+  WorkItem* d_items = nullptr;
+  int32_t* d_wg_off = nullptr;
+  RedTile* d_tiles = nullptr;
+  RedSrc* d_srcs = nullptr;
+  ~DevPlan();
+};
+
+}  // namespace paco
+
+struct paco_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cus = 0;
+  uint64_t budget = 0;
+  void* ws = nullptr;        // temporary faces
+  uint64_t ws_bytes = 0;
+  void* sws = nullptr;       // Strassen temporaries
+  uint64_t sws_bytes = 0;
+  double* d_verify = nullptr;  // 4 doubles + row list
+  int64_t* d_rows = nullptr;
+  int64_t rows_cap = 0;
+  std::map<std::string, std::unique_ptr<paco::DevPlan>> plans;
+  std::string last_error;
+};
+
+namespace paco {
+
+void set_err(paco_ctx ctx, const std::string& msg);
+paco_status hip_fail(paco_ctx ctx, hipError_t e, const char* what);
+paco_status upload_plan(paco_ctx ctx, DevPlan* dp);
+paco_status ensure_ws(paco_ctx ctx, uint64_t bytes);
+int choose_int_tile(const std::vector<Piece>& pcs);
+int choose_bool_tile(const std::vector<Piece>& pcs);
+int choose_ring_tile(const std::vector<Piece>& pcs, int prec);
+paco_status verify_sampled(paco_ctx ctx, int64_t n, int64_t m, int64_t k, const float* A, int64_t lda,
+                           const float* B, int64_t ldb, const float* C, int64_t ldc, int rows,
+                           uint64_t seed, paco_mm_result* res);
+void destroy_ctx_extras(paco_ctx ctx);
+
+}  // namespace paco

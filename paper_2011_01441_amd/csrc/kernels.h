@@ -1,0 +1,59 @@
+// kernels.h -- host-callable launchers of the HIP kernels (one per family).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_types.h"
+
+namespace paco {
+
+// Tile shapes of the integer (VALU) semiring kernel: output tile TM x TN,
+// k-step 32, 256 threads.
+enum IntTile : int { INT_T128x128 = 0, INT_T256x64 = 1, INT_T64x64 = 2, INT_T64x128 = 3 };
+struct IntTileShape { int tm, tn; };
+IntTileShape int_tile_shape(int tile);
+
+// Persistent semiring kernel: `nwg` workgroups; workgroup w runs the items
+// wg_off[q] .. wg_off[q+1] of processor q = remap(w).
+hipError_t launch_semiring_int(int sr, int tile, const ProbRef& pr, const WorkItem* items,
+                               const int32_t* wg_off, int nwg, int xcd_remap, void* ws,
+                               hipStream_t s);
+
+// Boolean OR-AND kernel on bit-packed words.
+// Tile shapes of the boolean kernel: TM rows x TNW words, 64 bits per step.
+enum BoolTile : int { BOOL_T512x32W = 0, BOOL_T128x128W = 1, BOOL_T256x64W = 2, BOOL_T64x64W = 3 };
+struct BoolTileShape { int tm, tnw; };
+BoolTileShape bool_tile_shape(int tile);
+hipError_t launch_semiring_bool(int tile, const ProbRef& pr, const WorkItem* items,
+                                const int32_t* wg_off, int nwg, int xcd_remap, void* ws,
+                                hipStream_t s);
+
+// (+,x) ring kernel on matrix cores.
+enum RingTile : int { RING_T128x128 = 0, RING_T64x64 = 1, RING_T256x128 = 2 };
+struct RingTileShape { int tm, tn, bk; };
+RingTileShape ring_tile_shape(int tile, int prec);
+hipError_t launch_ring(int prec, int tile, const ProbRef& pr, const WorkItem* items,
+                       const int32_t* wg_off, int nwg, int xcd_remap, void* ws, hipStream_t s);
+
+// Fold temporary faces into C (ascending k), one workgroup per tile.
+hipError_t launch_reduce(int sr, const ProbRef& pr, const RedTile* tiles, int ntiles,
+                         const RedSrc* srcs, const void* ws, hipStream_t s);
+
+// C = semiring zero (or unchanged when accumulating) for k = 0.
+hipError_t launch_fill_zero(int sr, void* C, int64_t rows, int64_t cols, int64_t ldc,
+                            hipStream_t s);
+
+// Float64 check of sampled rows: each of verify_blocks(m, nrows) blocks
+// writes 4 doubles to `part` (device): max rel, max abs, sum of squared
+// differences, sum of squared float64 values (see paco_verify_rows_f64).
+int64_t verify_blocks(int64_t m, int64_t nrows);
+hipError_t launch_verify_f64(int64_t n, int64_t m, int64_t k, const float* A, int64_t lda,
+                             const float* B, int64_t ldb, const float* C, int64_t ldc,
+                             const int64_t* rows, int64_t nrows, double* part, hipStream_t s);
+
+// Strassen two-level fused pre-add and combine (see k_strassen.hip).
+hipError_t launch_strassen_preadd(int levels, int64_t n, const float* A, const float* B,
+                                  float* S, float* T, hipStream_t s);
+hipError_t launch_strassen_combine(int levels, int64_t n, const float* M, float* C,
+                                   hipStream_t s);
+
+}  // namespace paco

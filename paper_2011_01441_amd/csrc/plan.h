@@ -1,0 +1,45 @@
+// plan.h -- turn partition pieces into device work lists and a k-cut
+// reduction plan.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+#include "device_types.h"
+#include "partition.h"
+
+namespace paco {
+
+// Geometry of one problem in kernel units (words for boolean m).
+struct ProbGeom {
+  int64_t n, m, k;
+};
+
+struct HostPlan {
+  int nwg = 0;                     // workgroups launched
+  bool xcd_remap = false;
+  std::vector<WorkItem> items;
+  std::vector<int32_t> wg_off;     // nwg + 1
+  std::vector<RedTile> tiles;
+  std::vector<RedSrc> srcs;
+  int64_t temp_elems = 0;          // workspace elements for temporary faces
+  // statistics over non-empty pieces
+  int32_t n_pieces = 0, n_kcuts = 0;
+  int64_t vmax = 0, vmin = 0;
+};
+
+// A piece tagged with the problem it belongs to (batched launches).
+struct TaggedPiece {
+  Piece pc;          // coordinates in the problem's kernel units
+  int32_t prob;
+  int32_t wg;        // workgroup (processor) index
+};
+
+// Build work lists for `nwg` workgroups from tagged pieces.  A piece whose
+// k0 > 0 writes its own temporary face (allocated after `temp_base`
+// elements); every covered C element then folds its faces in ascending-k
+// order.  `geom` gives each problem's C size (rows, cols in kernel units).
+HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_remap,
+                    const std::vector<ProbGeom>& geom, int64_t temp_base = 0);
+
+}  // namespace paco

@@ -1,0 +1,126 @@
+"""GPU parity: libpaco's HIP path against the CPU oracle on the same seeded
+inputs.  Integer and boolean results must be bit-exact; ring results within
+the componentwise bound max |C - C64| / (|A||B|) <= 2^-20."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2011_01441_amd")
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def comp_err(C, A, B):
+    C64, S = oracle.ring_f64(A, B, with_abs=True)
+    d = np.abs(C.astype(np.float64) - C64)
+    return float(np.max(np.where(S > 0, d / np.where(S > 0, S, 1), d)))
+
+
+# ---------------------------------------------------------------- (min,+)
+
+def test_minplus_config0_bit_exact(ctx):
+    print("case: minplus 384x320x256 seed 0", flush=True)
+    A, B = workloads.minplus_operands(384, 256, 320, seed=0)
+    C, res = ctx.semiring_mm(dev(A), dev(B), "minplus", return_result=True)
+    assert np.array_equal(host(C), oracle.minplus(A, B))
+    assert res["n_pieces"] == 256 and res["n_kcuts"] > 0
+
+
+@pytest.mark.parametrize("n,m,k", [(1, 1, 1), (5, 3, 2), (97, 130, 75), (300, 77, 129), (64, 64, 1000)])
+def test_minplus_ragged(ctx, n, m, k):
+    print(f"case: minplus {n}x{m}x{k}", flush=True)
+    A, B = workloads.minplus_operands(n, m, k, seed=n + m + k)
+    assert np.array_equal(host(ctx.semiring_mm(dev(A), dev(B), "minplus")), oracle.minplus(A, B))
+
+
+@pytest.mark.parametrize("p,part", [(1, "paco"), (3, "paco"), (257, "paco"), (256, "grid")])
+def test_minplus_partition_invariance(ctx, p, part):
+    print(f"case: minplus invariance p={p} {part}", flush=True)
+    A, B = workloads.minplus_operands(384, 256, 320, seed=0)
+    C = ctx.semiring_mm(dev(A), dev(B), "minplus", p=p, part=part)
+    assert np.array_equal(host(C), oracle.minplus(A, B))
+
+
+# ---------------------------------------------------------------- (max,+)
+
+@pytest.mark.parametrize("n,m,k", [(4096, 64, 512), (300, 77, 129), (33, 250, 64)])
+def test_maxplus_bit_exact(ctx, n, m, k):
+    print(f"case: maxplus {n}x{m}x{k}", flush=True)
+    A, B = workloads.maxplus_operands(n, m, k, seed=7)
+    A[3, :] = oracle.NEG_INF
+    assert np.array_equal(host(ctx.semiring_mm(dev(A), dev(B), "maxplus")), oracle.maxplus(A, B))
+
+
+# ---------------------------------------------------------------- boolean
+
+@pytest.mark.parametrize("n,m,k,dens", [(50, 100, 70, 0.05), (512, 1024, 2048, 0.0092),
+                                        (300, 33, 1000, 0.01), (1, 1, 1, 1.0)])
+def test_bool_bit_exact(ctx, n, m, k, dens):
+    print(f"case: bool {n}x{m}x{k} d={dens}", flush=True)
+    _, _, ap, bp = workloads.bool_operands(n, m, k, density=dens, seed=5)
+    Cw = ctx.semiring_mm(dev(ap.view(np.int32)), dev(bp.view(np.int32)), "bool", n=n, m=m, k=k)
+    assert np.array_equal(host(Cw).view(np.uint32), oracle.bool_packed(ap, bp, n, m, k))
+
+
+# ---------------------------------------------------------------- ring
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("n,m,k", [(70, 90, 300), (256, 512, 1024), (33, 17, 65)])
+def test_ring_small_integers_exact(ctx, prec, n, m, k):
+    print(f"case: ring small-int {prec} {n}x{m}x{k}", flush=True)
+    A, B = workloads.small_int_operands(n, m, k, seed=k)
+    C = host(ctx.semiring_mm(dev(A), dev(B), "ring", precision=prec))
+    assert np.array_equal(C.astype(np.float64), oracle.ring_f64(A, B))
+
+
+@pytest.mark.parametrize("prec,k", [("fp32", 512), ("bf16x3", 4096), ("bf16x6", 256)])
+def test_ring_normal_within_bound(ctx, prec, k):
+    print(f"case: ring normal {prec} k={k}", flush=True)
+    A, B = workloads.ring_operands(200, 300, k, seed=3)
+    C = host(ctx.semiring_mm(dev(A), dev(B), "ring", precision=prec))
+    assert comp_err(C, A, B) <= 2.0 ** -20
+
+
+def test_ring_verify_rows_matches_oracle(ctx):
+    print("case: ring verify", flush=True)
+    A, B = workloads.ring_operands(64, 96, 700, seed=4)
+    Ad, Bd = dev(A), dev(B)
+    C, res = ctx.semiring_mm(Ad, Bd, "ring", precision="bf16x3", verify_rows=64,
+                             return_result=True)
+    Ch = host(C)
+    C64, S = oracle.ring_f64(A, B, with_abs=True)
+    rel = np.max(np.abs(Ch - C64) / S)
+    assert res["verify_max_rel"] == pytest.approx(rel, rel=1e-9)
+
+
+# ---------------------------------------------------------------- Strassen
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_strassen_small_integers_exact(ctx, levels):
+    print(f"case: strassen small-int L={levels}", flush=True)
+    A, B = workloads.small_int_operands(256, 256, 256, seed=9)
+    C = host(ctx.strassen_mm(dev(A), dev(B), levels=levels, leaf="bf16x3"))
+    expect = oracle.strassen_i64(A.astype(np.int64), B.astype(np.int64), levels)
+    assert np.array_equal(C.astype(np.int64), expect)
