@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Benchmark of libpaco on one MI355X: PACO-partitioned semiring MM.
+
+Default workload: the (+,x) ring with long k, A 2048x65536 times
+B 65536x1024, float32 N(0,1), bf16x3 split-precision matrix-core path,
+MM-1-Piece over the 256 compute units.  A step is one library call
+(partition plan cached, piece execution, k-cut reduction) with operands
+resident in HBM.  The same call on a plain output-tile grid with an
+autotuned split-k is timed beside it, the float64 sampled-row error is
+reported, and the CPU oracle is timed on a bounded row sample.
+
+Prints ONE JSON line.  `--workload` selects another shape for profiling.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "semiring-MM GOP/s and % roofline, PACO vs plain tile grid; server p50/p99 latency"
+# MI355X published peaks; int32 VALU derived: 256 CUs x 64 lanes x 2.4 GHz
+PEAK = {"bf16": 2500.0, "fp32": 157.3, "int32": 39.3, "hbm": 8000.0}
+
+WORKLOADS = {
+    "ring_longk": dict(kind="ring", n=2048, m=1024, k=65536, prec="bf16x3",
+                       desc="(+,x) ring long k: A 2048x65536 f32 N(0,1), B 65536x1024, bf16x3"),
+    "ring_longk_fp32": dict(kind="ring", n=2048, m=1024, k=65536, prec="fp32",
+                            desc="(+,x) ring long k, plain float32 matrix-core path"),
+    "ring_square": dict(kind="ring", n=8192, m=8192, k=8192, prec="bf16x3",
+                        desc="(+,x) ring 8192^3 f32 N(0,1), bf16x3"),
+    "minplus_c0": dict(kind="minplus", n=384, m=256, k=320,
+                       desc="(min,+) int32 A 384x320, B 320x256, U[0,2^20) with 5% INF"),
+    "minplus_8192": dict(kind="minplus", n=8192, m=8192, k=8192,
+                         desc="(min,+) int32 8192^3, U[0,2^20) with 5% INF"),
+    "maxplus_c2a": dict(kind="maxplus", n=131072, m=64, k=512,
+                        desc="(max,+) int32 A 131072x512, B 512x64, U[-2^15,2^15)"),
+    "bool_c2b": dict(kind="bool", n=8192, m=8192, k=8192, density=0.05,
+                     desc="boolean OR-AND 8192^3 bits, density 0.05, packed uint32"),
+    "strassen_c3": dict(kind="strassen", n=16384, levels=2, prec="bf16x3",
+                        desc="Strassen 2 levels, n=16384 f32 U[-1,1], bf16x3 leaf"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(w, torch, dev):
+    import workloads as W
+    kind = w["kind"]
+    t0 = time.time()
+    if kind == "ring":
+        A, B = W.ring_operands(w["n"], w["m"], w["k"], seed=0)
+    elif kind == "minplus":
+        A, B = W.minplus_operands(w["n"], w["m"], w["k"], seed=0)
+    elif kind == "maxplus":
+        A, B = W.maxplus_operands(w["n"], w["m"], w["k"], seed=0)
+    elif kind == "bool":
+        A, B = W.bool_operands_packed(w["n"], w["m"], w["k"], density=w["density"], seed=0)
+        A, B = A.view(np.int32), B.view(np.int32)
+    elif kind == "strassen":
+        A, B = W.strassen_operands(w["n"], seed=0)
+    log(f"inputs generated in {time.time() - t0:.1f}s")
+    return A, B, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+
+
+def algorithmic(w, prec):
+    """(work per call, unit, bound, peak) of the dominant kernel."""
+    kind = w["kind"]
+    if kind in ("ring", "strassen"):
+        if kind == "ring":
+            nmk = w["n"] * w["m"] * w["k"]
+        else:
+            h = w["n"] >> w["levels"]
+            nmk = (7 ** w["levels"]) * h ** 3
+        mult = {"bf16x3": 3, "bf16x6": 6, "fp32": 1}[prec]
+        flops = 2.0 * nmk * mult
+        return flops, "TFLOP/s", "mfma", PEAK["fp32" if prec == "fp32" else "bf16"]
+    if kind in ("minplus", "maxplus"):
+        return 2.0 * w["n"] * w["m"] * w["k"], "Tops/s", "alu", PEAK["int32"]
+    if kind == "bool":
+        return 2.0 * w["n"] * w["k"] * math.ceil(w["m"] / 32), "Tops/s", "alu", PEAK["int32"]
+    raise ValueError(kind)
+
+
+def classic_ops(w):
+    if w["kind"] == "strassen":
+        return 2.0 * w["n"] ** 3
+    return 2.0 * w["n"] * w["m"] * w["k"]
+
+
+def call(ctx, w, Ad, Bd, C, **kw):
+    kind = w["kind"]
+    if kind == "strassen":
+        return ctx.strassen_mm(Ad, Bd, levels=w["levels"], leaf=w["prec"], C=C)
+    if kind == "bool":
+        return ctx.semiring_mm(Ad, Bd, "bool", n=w["n"], m=w["m"], k=w["k"], C=C, **kw)
+    if kind == "ring":
+        return ctx.semiring_mm(Ad, Bd, "ring", C=C, precision=w["prec"], **kw)
+    return ctx.semiring_mm(Ad, Bd, kind, C=C, **kw)
+
+
+def timed(torch, fn, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(w, A, B, target_s):
+    """The oracle as it stands, on a bounded row sample of the same inputs."""
+    import oracle
+    thr = oracle.num_threads()
+    kind = w["kind"]
+    n = w["n"]
+    if kind == "strassen":
+        m = k = w["n"]
+    else:
+        m, k = w["m"], w["k"]
+    rows = max(1, min(n, thr))
+    while True:
+        idx = np.linspace(0, n - 1, rows).astype(np.int64)
+        t0 = time.perf_counter()
+        if kind in ("ring", "strassen"):
+            oracle.ring_f64(A, B, rows=idx)
+        elif kind == "minplus":
+            oracle.minplus(A[idx], B)
+        elif kind == "maxplus":
+            oracle.maxplus(A[idx], B)
+        elif kind == "bool":
+            oracle.bool_packed(A[idx].view(np.uint32), B.view(np.uint32), rows, m, k)
+        dt = time.perf_counter() - t0
+        if dt >= target_s / 4 or rows >= n:
+            break
+        rows = min(n, int(rows * max(2.0, target_s / max(dt, 1e-3) / 1.5)))
+    ops = 2.0 * rows * m * k   # same unit as the GPU value: one (x) and one (+) per (i, j, l)
+    return {"value": ops / dt / 1e9, "unit": "GOP/s", "cores": thr, "kind": "oracle",
+            "sample": f"{rows} of {n} output rows (full width), float64/int64 triple loop, "
+                      f"{dt:.1f} s", "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ring_longk", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-grid", action="store_true", help="skip the plain tile-grid baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--verify-rows", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2011_01441_amd as P
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    A, B, Ad, Bd = make_inputs(w, torch, dev)
+    ctx = P.Context(0)
+    prec = w.get("prec", "int")
+    if w["kind"] == "bool":
+        C = torch.empty((w["n"], (w["m"] + 31) // 32), dtype=torch.int32, device=dev)
+    elif w["kind"] == "strassen":
+        C = torch.empty((w["n"], w["n"]), dtype=torch.float32, device=dev)
+    else:
+        C = torch.empty((w["n"], w["m"]), dtype=Ad.dtype, device=dev)
+
+    # ---- PACO path
+    res = None
+    for _ in range(args.warmup):
+        if w["kind"] == "strassen":
+            call(ctx, w, Ad, Bd, C)
+        else:
+            _, res = call(ctx, w, Ad, Bd, C, return_result=True)
+    log("warmup done")
+    ctx.timing(True)
+    ms = timed(torch, lambda: call(ctx, w, Ad, Bd, C), args.steps) * 1e3
+    tm = ctx.timing()
+    ctx.timing(False)
+    kern_ms = tm["main_ms"] / max(tm["launches"], 1)
+    red_ms = tm["reduce_ms"] / max(tm["launches"], 1)
+    other_ms = tm["other_ms"] / max(tm["launches"], 1)
+    log(f"paco: {ms:.3f} ms/step, kernel {kern_ms:.3f} ms, reduce {red_ms:.3f} ms, other {other_ms:.3f} ms")
+    work, unit, bound, peak = algorithmic(w, prec)
+    achieved = work / (kern_ms * 1e-3) / 1e12
+    value = classic_ops(w) / (ms * 1e-3) / 1e9
+
+    # ---- plain tile grid (same microkernels), split-k autotuned
+    grid = None
+    if not args.no_grid and w["kind"] != "strassen":
+        best = None
+        for sk in (1, 2, 4, 8, 16, 32, 64):
+            f = (lambda sk=sk: call(ctx, w, Ad, Bd, C, part="grid", split_k=sk))
+            f()
+            t = timed(torch, f, 3) * 1e3
+            if best is None or t < best[1]:
+                best = (sk, t)
+        gms = timed(torch, lambda: call(ctx, w, Ad, Bd, C, part="grid", split_k=best[0]),
+                    args.steps) * 1e3
+        grid = {"value": classic_ops(w) / (gms * 1e-3) / 1e9, "ms_per_step": round(gms, 4),
+                "split_k": best[0]}
+        log(f"grid: {gms:.3f} ms/step (split_k {best[0]})")
+
+    # ---- accuracy of this result
+    err = None
+    if w["kind"] == "ring":
+        _, r = call(ctx, w, Ad, Bd, C, verify_rows=args.verify_rows, return_result=True)
+        err = {"max_rel_componentwise_sampled": r["verify_max_rel"], "rows": args.verify_rows,
+               "bound": 2.0 ** -20, "log2": math.log2(r["verify_max_rel"]) if r["verify_max_rel"] > 0 else None}
+    elif w["kind"] == "strassen":
+        call(ctx, w, Ad, Bd, C)
+        rows = torch.arange(0, w["n"], max(1, w["n"] // 64), device=dev)
+        mrel, mabs, sd, sr = ctx.verify_rows(Ad, Bd, C, rows)
+        err = {"normwise_sampled": math.sqrt(sd / sr) if sr > 0 else None,
+               "max_rel_componentwise_sampled": mrel, "rows": int(rows.numel()), "bound": 2.0 ** -16}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, A, B, args.cpu_seconds)
+        log(f"cpu oracle: {cpu['value']:.3f} GOP/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"ring": "bf16" if prec != "fp32" else "f32", "strassen": "bf16",
+                  "minplus": "u32", "maxplus": "i32", "bool": "u32"}[w["kind"]],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "desc": w["desc"], "precision": prec,
+                   "partition": "PACO MM-1-Piece", "p": res["p"] if res else None,
+                   "pieces": res["n_pieces"] if res else None,
+                   "kcut_faces": res["n_kcuts"] if res else None,
+                   "parallelism": "one GPU, 256 CUs"},
+        "roofline": {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel_ms": round(kern_ms, 4), "reduce_ms": round(red_ms, 4),
+                     "other_ms": round(other_ms, 4), "work_per_launch": work},
+        "grid_baseline": grid,
+        "paco_vs_grid": round(grid["ms_per_step"] / ms, 4) if grid else None,
+        "error": err,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -176,6 +176,22 @@ paco_status paco_verify_rows_f64(paco_ctx ctx, int64_t n, int64_t m, int64_t k,
                                  const float* A, const float* B, const float* C,
                                  const int64_t* rows, int64_t nrows, double* out);
 
+/* --------------------------------------------------------------- timing */
+
+/* Per-kernel timing for profiling.  While enabled, every call records HIP
+ * events on the context stream around each kernel it launches.  `read`
+ * synchronises the stream, sums the elapsed times by kernel role since the
+ * last read (or enable) and clears them. */
+typedef struct paco_timing {
+  int32_t launches;     /* main-kernel launches timed */
+  double main_ms;       /* semiring / ring kernels (the piece execution) */
+  double reduce_ms;     /* k-cut reductions */
+  double other_ms;      /* Strassen pre-add and combine, fills */
+} paco_timing;
+
+paco_status paco_timing_enable(paco_ctx ctx, int enable);
+paco_status paco_timing_read(paco_ctx ctx, paco_timing* out);
+
 /* ------------------------------------------------------------ partition */
 
 typedef struct paco_piece {
@@ -203,6 +219,31 @@ typedef struct paco_part_opts {
  * pruned-BFS assignment of section "PACO MM". */
 paco_status paco_partition(int64_t n, int64_t m, int64_t k, const paco_part_opts* opts,
                            paco_piece* out, int64_t cap, int64_t* n_out);
+
+/* Host-only introspection of the plan a semiring MM call launches (for
+ * tests and tools; no device is touched).  Call once with all arrays NULL
+ * to get the sizes in *info, then again with arrays of at least those sizes
+ * (the counts in *info on input are the capacities):
+ *   items : n_items x 8 int64 (prob, n0, n1, m0, m1, k0, k1, out_off), in
+ *           kernel units (boolean m counts words); out_off < 0 writes C,
+ *           otherwise a temporary face of (n1-n0) x (m1-m0) elements at
+ *           that workspace offset;
+ *   wg_off: n_wg + 1 int32, items of workgroup q are wg_off[q]..wg_off[q+1];
+ *   tiles : n_tiles x 7 int32 (prob, i0, i1, j0, j1, s0, s1), reduction
+ *           rectangles of C that fold sources s0..s1-1 in order;
+ *   srcs  : n_srcs x 4 int64 (off, ld, r0, c0), element (i, j) of a source
+ *           at workspace offset off + (i - r0) * ld + (j - c0).
+ * num_cus is the processor count used for the grid's default split-k. */
+typedef struct paco_plan_info {
+  int32_t n_wg, n_items, n_tiles, n_srcs;
+  int32_t tile, red_vec, xcd_remap;
+  int64_t temp_elems;
+} paco_plan_info;
+
+paco_status paco_plan_export(int64_t n, int64_t m, int64_t k, paco_semiring sr, paco_part_mode part,
+                             int32_t p, int32_t split_k, paco_precision prec, int32_t num_cus,
+                             paco_plan_info* info, int64_t* items, int32_t* wg_off, int32_t* tiles,
+                             int64_t* srcs);
 
 #ifdef __cplusplus
 }

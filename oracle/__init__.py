@@ -38,6 +38,7 @@ def lib():
         L.oracle_ring_i64.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64]
         L.oracle_strassen_f64.argtypes = [i64, vp, vp, vp, ci]
         L.oracle_strassen_i64.argtypes = [i64, vp, vp, vp, ci]
+        L.oracle_num_threads.restype = ci
         _lib = L
     return _lib
 
@@ -157,3 +158,7 @@ def unpack_bits(W, cols):
     for c in range(cols):
         out[:, c] = (W[:, c // 32] >> np.uint32(c % 32)) & np.uint32(1)
     return out
+
+
+def num_threads():
+    return lib().oracle_num_threads()

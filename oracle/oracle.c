@@ -42,6 +42,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_INF ((int64_t)1 << 30)
 #define OR_NEG_INF (-((int64_t)1 << 30))
@@ -260,4 +263,13 @@ void oracle_strassen_f64(int64_t n, const double* A, const double* B,
 void oracle_strassen_i64(int64_t n, const int64_t* A, const int64_t* B,
                          int64_t* C, int levels) {
   strassen_i64_rec(n, A, n, B, n, C, n, levels);
+}
+
+/* Threads an OpenMP loop of this library runs on (1 without OpenMP). */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -11,7 +11,7 @@ import os
 
 import torch
 
-__all__ = ["Context", "PacoError", "semiring_mm", "strassen_mm", "partition", "lib",
+__all__ = ["Context", "PacoError", "semiring_mm", "strassen_mm", "partition", "plan_export", "lib",
            "SEMIRING", "PRECISION", "INF", "NEG_INF", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -58,6 +58,17 @@ class Piece(ctypes.Structure):
                 ("round", ctypes.c_int32), ("depth", ctypes.c_int32)]
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int32), ("main_ms", ctypes.c_double),
+                ("reduce_ms", ctypes.c_double), ("other_ms", ctypes.c_double)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_wg", ctypes.c_int32), ("n_items", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
+                ("n_srcs", ctypes.c_int32), ("tile", ctypes.c_int32), ("red_vec", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32), ("temp_elems", ctypes.c_int64)]
+
+
 class PartOpts(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("q_n", ctypes.c_int32), ("q_m", ctypes.c_int32),
                 ("q_k", ctypes.c_int32), ("weights", ctypes.POINTER(ctypes.c_double)),
@@ -93,7 +104,11 @@ def lib():
                                        ctypes.POINTER(ctypes.c_double)]
     L.paco_partition.argtypes = [i64, i64, i64, ctypes.POINTER(PartOpts), ctypes.POINTER(Piece),
                                  i64, ctypes.POINTER(i64)]
-    for name in ("paco_create", "paco_destroy", "paco_set_stream", "paco_semiring_mm",
+    L.paco_plan_export.argtypes = [i64, i64, i64, ci, ci, ctypes.c_int32, ctypes.c_int32, ci,
+                                   ctypes.c_int32, ctypes.POINTER(PlanInfo), vp, vp, vp, vp]
+    L.paco_timing_enable.argtypes = [vp, ci]
+    L.paco_timing_read.argtypes = [vp, ctypes.POINTER(Timing)]
+    for name in ("paco_plan_export", "paco_timing_enable", "paco_timing_read", "paco_create", "paco_destroy", "paco_set_stream", "paco_semiring_mm",
                  "paco_semiring_mm_ex", "paco_strassen_mm", "paco_verify_rows_f64",
                  "paco_partition"):
         getattr(L, name).restype = ci
@@ -122,6 +137,25 @@ def partition(n, m, k, p, q=(1, 1, 1), weights=None, multi_piece=False):
     _check(L.paco_partition(n, m, k, ctypes.byref(o), buf, cnt.value, ctypes.byref(cnt)))
     names = [f[0] for f in Piece._fields_]
     return [{f: getattr(buf[i], f) for f in names} for i in range(cnt.value)]
+
+
+def plan_export(n, m, k, semiring, part="paco", p=256, split_k=0, precision="auto",
+                num_cus=256):
+    """Host-only: the work plan of a semiring MM call, as numpy arrays
+    (items n x 8, wg_off, tiles n x 7, srcs n x 4) plus an info dict."""
+    import numpy as np
+    L = lib()
+    info = PlanInfo()
+    args = (n, m, k, SEMIRING[semiring], PART[part], p, split_k, PRECISION[precision], num_cus)
+    _check(L.paco_plan_export(*args, ctypes.byref(info), None, None, None, None))
+    items = np.zeros((max(info.n_items, 1), 8), np.int64)
+    wg = np.zeros(info.n_wg + 1, np.int32)
+    tiles = np.zeros((max(info.n_tiles, 1), 7), np.int32)
+    srcs = np.zeros((max(info.n_srcs, 1), 4), np.int64)
+    ptr = lambda a: ctypes.c_void_p(a.ctypes.data)
+    _check(L.paco_plan_export(*args, ctypes.byref(info), ptr(items), ptr(wg), ptr(tiles), ptr(srcs)))
+    d = {f[0]: getattr(info, f[0]) for f in PlanInfo._fields_}
+    return (items[:info.n_items], wg, tiles[:info.n_tiles], srcs[:info.n_srcs], d)
 
 
 def _ptr(t):
@@ -212,6 +246,16 @@ class Context:
         _check(self._L.paco_strassen_mm(self._h, n, _ptr(A), _ptr(B), _ptr(C), levels,
                                         PRECISION[leaf]), self._h)
         return C
+
+    def timing(self, enable=None):
+        """timing(True) starts per-kernel event timing; timing() reads and
+        clears it: dict(launches, main_ms, reduce_ms, other_ms)."""
+        if enable is not None:
+            _check(self._L.paco_timing_enable(self._h, 1 if enable else 0), self._h)
+            return None
+        t = Timing()
+        _check(self._L.paco_timing_read(self._h, ctypes.byref(t)), self._h)
+        return {f[0]: getattr(t, f[0]) for f in Timing._fields_}
 
     def verify_rows(self, A, B, C, rows):
         """float64 check of the listed rows: (max rel, max abs, sum sq diff, sum sq ref)."""

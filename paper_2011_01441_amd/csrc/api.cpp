@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -102,7 +103,65 @@ int choose_int_tile(const std::vector<Piece>& pcs) {
   return best;
 }
 
+static hipEvent_t take_event(paco_ctx ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+TimeScope::TimeScope(paco_ctx c, int r) : ctx(c), role(r) {
+  if (!ctx->timing) return;
+  a = take_event(ctx);
+  if (a) (void)hipEventRecord(a, ctx->stream);
+}
+
+TimeScope::~TimeScope() {
+  if (!a) return;
+  hipEvent_t b = take_event(ctx);
+  if (!b) {
+    ctx->event_pool.push_back(a);
+    return;
+  }
+  (void)hipEventRecord(b, ctx->stream);
+  ctx->marks.push_back({a, b, role});
+}
+
 }  // namespace paco
+
+extern "C" paco_status paco_timing_enable(paco_ctx ctx, int enable) {
+  if (!ctx) return PACO_ERR_INVALID_ARG;
+  ctx->timing = enable != 0;
+  return PACO_OK;
+}
+
+extern "C" paco_status paco_timing_read(paco_ctx ctx, paco_timing* out) {
+  if (!ctx || !out) return PACO_ERR_INVALID_ARG;
+  memset(out, 0, sizeof *out);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "timing sync");
+  for (auto& mk : ctx->marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, mk.a, mk.b) == hipSuccess) {
+      if (mk.role == 0) {
+        out->main_ms += ms;
+        out->launches += 1;
+      } else if (mk.role == 1) {
+        out->reduce_ms += ms;
+      } else {
+        out->other_ms += ms;
+      }
+    }
+    ctx->event_pool.push_back(mk.a);
+    ctx->event_pool.push_back(mk.b);
+  }
+  ctx->marks.clear();
+  return PACO_OK;
+}
 
 // ------------------------------------------------------------------ context
 
@@ -128,6 +187,11 @@ extern "C" paco_status paco_destroy(paco_ctx ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   ctx->plans.clear();
+  for (auto& mk : ctx->marks) {
+    (void)hipEventDestroy(mk.a);
+    (void)hipEventDestroy(mk.b);
+  }
+  for (hipEvent_t ev : ctx->event_pool) (void)hipEventDestroy(ev);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->d_verify) (void)hipFree(ctx->d_verify);
   destroy_ctx_extras(ctx);
@@ -215,6 +279,109 @@ int auto_precision(int64_t k) {
 
 }  // namespace
 
+namespace paco {
+
+// Host part of a semiring MM plan: partition, tile choice, work lists.
+void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
+                  int num_cus, DevPlan* np) {
+  const bool is_bool = sr == PACO_SR_OR_AND_B1;
+  const int64_t mu = is_bool ? words(m) : m, ku = is_bool ? words(k) : k;
+  const int fam = sr == PACO_SR_PLUS_TIMES_F32 ? 2 : (is_bool ? 1 : 0);
+  std::vector<Piece> pcs;
+  int tile = 0, tm = 0, tn = 0, bk = 32;
+  if (part == PACO_PART_PACO) {
+    PartOpts po;
+    po.p = p;
+    if (fam == 1) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
+    else if (fam == 2) { po.q[0] = 16; po.q[1] = 16; po.q[2] = 32; }
+    pcs = partition_mm1(n, m, k, po);
+    if (fam == 1)  // bits -> words in m
+      for (Piece& pc : pcs) { pc.m0 /= 32; pc.m1 = words(pc.m1); }
+    if (fam == 0) tile = choose_int_tile(pcs);
+    else if (fam == 1) tile = choose_bool_tile(pcs);
+    else tile = choose_ring_tile(pcs, prec);
+    if (fam == 2 && getenv("PACO_RING_TILE")) tile = atoi(getenv("PACO_RING_TILE"));
+  } else {
+    if (fam == 0) {
+      tile = m <= 64 ? INT_T256x64 : INT_T128x128;
+      IntTileShape ts = int_tile_shape(tile);
+      tm = ts.tm; tn = ts.tn;
+    } else if (fam == 1) {
+      tile = BOOL_T128x128W;
+      BoolTileShape ts = bool_tile_shape(tile);
+      tm = ts.tm; tn = ts.tnw * 32;
+    } else {
+      tile = RING_T128x128;
+      if (getenv("PACO_RING_TILE")) tile = atoi(getenv("PACO_RING_TILE"));
+      RingTileShape ts = ring_tile_shape(tile, prec);
+      tm = ts.tm; tn = ts.tn; bk = ts.bk;
+    }
+    int64_t tiles = ((n + tm - 1) / tm) * ((m + tn - 1) / tn);
+    int64_t kb = (k + bk - 1) / bk;
+    int sk = split_k;
+    if (sk <= 0) sk = (int)std::max<int64_t>(1, std::min<int64_t>(kb, (num_cus + tiles - 1) / tiles));
+    pcs = partition_grid(n, m, k, tm, tn, bk, sk);
+    if (fam == 1)
+      for (Piece& pc : pcs) { pc.m0 /= 32; pc.m1 = words(pc.m1); }
+  }
+  std::vector<TaggedPiece> tp(pcs.size());
+  for (size_t i = 0; i < pcs.size(); ++i) tp[i] = {pcs[i], 0, part == PACO_PART_PACO ? pcs[i].proc : (int)i};
+  const int nwg = part == PACO_PART_PACO ? p : (int)pcs.size();
+  std::vector<ProbGeom> geom{{n, mu, ku}};
+  np->h = build_plan(tp, nwg, part == PACO_PART_PACO, geom);
+  np->tile = tile;
+  np->fam = fam;
+  np->p = p;
+}
+
+}  // namespace paco
+
+extern "C" paco_status paco_plan_export(int64_t n, int64_t m, int64_t k, paco_semiring sr, paco_part_mode part,
+                                        int32_t p, int32_t split_k, paco_precision prec, int32_t num_cus,
+                                        paco_plan_info* info, int64_t* items, int32_t* wg_off, int32_t* tiles,
+                                        int64_t* srcs) {
+  if (!info || n <= 0 || m <= 0 || k <= 0 || n >= (1ll << 31) || m >= (1ll << 31) || k >= (1ll << 31) ||
+      sr < PACO_SR_PLUS_TIMES_F32 || sr > PACO_SR_OR_AND_B1 || part < PACO_PART_PACO || part > PACO_PART_GRID ||
+      p < 1 || p > 65536 || split_k < 0 || num_cus < 1 || prec < PACO_PREC_FP32 || prec > PACO_PREC_AUTO)
+    return PACO_ERR_INVALID_ARG;
+  int pr = -1;
+  if (sr == PACO_SR_PLUS_TIMES_F32) pr = prec == PACO_PREC_AUTO ? auto_precision(k) : (int)prec;
+  DevPlan dp;
+  make_mm_plan((int)sr, n, m, k, (int)part, p, split_k, pr, num_cus, &dp);
+  const HostPlan& h = dp.h;
+  const bool fill = items && wg_off && tiles && srcs;
+  if (fill) {
+    if (info->n_items < (int32_t)h.items.size() || info->n_wg < h.nwg || info->n_tiles < (int32_t)h.tiles.size() ||
+        info->n_srcs < (int32_t)h.srcs.size())
+      return PACO_ERR_INVALID_ARG;
+    for (size_t i = 0; i < h.items.size(); ++i) {
+      const WorkItem& w = h.items[i];
+      int64_t* o = items + 8 * i;
+      o[0] = w.prob; o[1] = w.n0; o[2] = w.n1; o[3] = w.m0; o[4] = w.m1; o[5] = w.k0; o[6] = w.k1; o[7] = w.out_off;
+    }
+    for (int i = 0; i <= h.nwg; ++i) wg_off[i] = h.wg_off[i];
+    for (size_t i = 0; i < h.tiles.size(); ++i) {
+      const RedTile& t = h.tiles[i];
+      int32_t* o = tiles + 7 * i;
+      o[0] = t.prob; o[1] = t.i0; o[2] = t.i1; o[3] = t.j0; o[4] = t.j1; o[5] = t.s0; o[6] = t.s1;
+    }
+    for (size_t i = 0; i < h.srcs.size(); ++i) {
+      const RedSrc& r = h.srcs[i];
+      int64_t* o = srcs + 4 * i;
+      o[0] = r.off; o[1] = r.ld; o[2] = r.r0; o[3] = r.c0;
+    }
+  }
+  info->n_wg = h.nwg;
+  info->n_items = (int32_t)h.items.size();
+  info->n_tiles = (int32_t)h.tiles.size();
+  info->n_srcs = (int32_t)h.srcs.size();
+  info->tile = dp.tile;
+  info->red_vec = h.red_vec;
+  info->xcd_remap = h.xcd_remap ? 1 : 0;
+  info->temp_elems = h.temp_elems;
+  return PACO_OK;
+}
+
 paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res);
 
 extern "C" paco_status paco_semiring_mm(paco_ctx ctx, int64_t n, int64_t m, int64_t k,
@@ -287,6 +454,7 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   if (z.k == 0) {
     if (d->accumulate) return PACO_OK;
+    TimeScope ts(ctx, 2);
     e = launch_fill_zero(is_bool ? SR_BOOL : (int)d->sr, d->C, z.n, z.mu, z.ldc, ctx->stream);
     return e == hipSuccess ? PACO_OK : hip_fail(ctx, e, "fill");
   }
@@ -311,51 +479,8 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
     dp = itp->second.get();
   } else {
     std::unique_ptr<DevPlan> np(new DevPlan());
-    int fam = d->sr == PACO_SR_PLUS_TIMES_F32 ? 2 : (is_bool ? 1 : 0);
-    std::vector<Piece> pcs;
-    int tile = 0, tm = 0, tn = 0, bk = 32;
-    if (d->part == PACO_PART_PACO) {
-      PartOpts po;
-      po.p = p;
-      if (fam == 1) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
-      else if (fam == 2) { po.q[0] = 16; po.q[1] = 16; po.q[2] = 32; }
-      pcs = partition_mm1(z.n, z.m, z.k, po);
-      if (fam == 1) {  // bits -> words in m
-        for (Piece& pc : pcs) { pc.m0 /= 32; pc.m1 = words(pc.m1); }
-      }
-      if (fam == 0) tile = choose_int_tile(pcs);
-      else if (fam == 1) tile = choose_bool_tile(pcs);
-      else tile = choose_ring_tile(pcs, z.prec);
-    } else {
-      if (fam == 0) {
-        tile = z.m <= 64 ? INT_T256x64 : INT_T128x128;
-        IntTileShape ts = int_tile_shape(tile);
-        tm = ts.tm; tn = ts.tn;
-      } else if (fam == 1) {
-        tile = BOOL_T128x128W;
-        BoolTileShape ts = bool_tile_shape(tile);
-        tm = ts.tm; tn = ts.tnw * 32;
-      } else {
-        tile = RING_T128x128;
-        RingTileShape ts = ring_tile_shape(tile, z.prec);
-        tm = ts.tm; tn = ts.tn; bk = ts.bk;
-      }
-      int64_t tiles = ((z.n + tm - 1) / tm) * ((z.m + tn - 1) / tn);
-      int64_t kb = (z.k + bk - 1) / bk;
-      int sk = d->grid_split_k;
-      if (sk <= 0) sk = (int)std::max<int64_t>(1, std::min<int64_t>(kb, (ctx->num_cus + tiles - 1) / tiles));
-      pcs = partition_grid(z.n, z.m, z.k, tm, tn, bk, sk);
-      if (fam == 1)
-        for (Piece& pc : pcs) { pc.m0 /= 32; pc.m1 = words(pc.m1); }
-    }
-    std::vector<TaggedPiece> tp(pcs.size());
-    for (size_t i = 0; i < pcs.size(); ++i) tp[i] = {pcs[i], 0, d->part == PACO_PART_PACO ? pcs[i].proc : (int)i};
-    int nwg = d->part == PACO_PART_PACO ? p : (int)pcs.size();
-    std::vector<ProbGeom> geom{{z.n, z.mu, z.ku}};
-    np->h = build_plan(tp, nwg, d->part == PACO_PART_PACO, geom);
-    np->tile = tile;
-    np->fam = fam;
-    np->p = p;
+    make_mm_plan((int)d->sr, z.n, z.m, z.k, (int)d->part, p, d->grid_split_k, z.prec, ctx->num_cus,
+                 np.get());
     paco_status st = upload_plan(ctx, np.get());
     if (st != PACO_OK) return st;
     dp = np.get();
@@ -373,6 +498,8 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   pr.base.lda = z.lda; pr.base.ldb = z.ldb; pr.base.ldc = z.ldc;
   pr.base.n = (int32_t)z.n; pr.base.m = (int32_t)z.m; pr.base.k = (int32_t)z.k;
   pr.base.accumulate = d->accumulate ? 1 : 0;
+  {
+  TimeScope ts(ctx, 0);
   if (dp->fam == 0)
     e = launch_semiring_int((int)d->sr, dp->tile, pr, dp->d_items, dp->d_wg_off, dp->h.nwg,
                             dp->h.xcd_remap, ctx->ws, ctx->stream);
@@ -382,10 +509,13 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   else
     e = launch_ring(z.prec, dp->tile, pr, dp->d_items, dp->d_wg_off, dp->h.nwg, dp->h.xcd_remap,
                     ctx->ws, ctx->stream);
+  }
   if (e != hipSuccess) return hip_fail(ctx, e, "semiring kernel launch");
   if (!dp->h.tiles.empty()) {
+    TimeScope ts(ctx, 1);
+    const int rvec = (dp->h.red_vec == 4 && (uintptr_t)d->C % 16 == 0 && z.ldc % 4 == 0) ? 4 : 1;
     e = launch_reduce(is_bool ? SR_BOOL : (int)d->sr, pr, dp->d_tiles, (int)dp->h.tiles.size(),
-                      dp->d_srcs, ctx->ws, ctx->stream);
+                      dp->d_srcs, ctx->ws, ctx->stream, rvec);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
   }
   if (res) {

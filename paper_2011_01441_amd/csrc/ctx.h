@@ -42,6 +42,14 @@ struct paco_ctx_s {
   int64_t rows_cap = 0;
   std::map<std::string, std::unique_ptr<paco::DevPlan>> plans;
   std::string last_error;
+  // per-kernel timing (paco_timing_enable)
+  bool timing = false;
+  struct Mark {
+    hipEvent_t a, b;
+    int role;  // 0 main, 1 reduce, 2 other
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> event_pool;
 };
 
 namespace paco {
@@ -57,5 +65,14 @@ paco_status verify_sampled(paco_ctx ctx, int64_t n, int64_t m, int64_t k, const 
                            const float* B, int64_t ldb, const float* C, int64_t ldc, int rows,
                            uint64_t seed, paco_mm_result* res);
 void destroy_ctx_extras(paco_ctx ctx);
+
+// Brackets one kernel launch with timing events when timing is enabled.
+struct TimeScope {
+  paco_ctx ctx;
+  int role;
+  hipEvent_t a = nullptr;
+  TimeScope(paco_ctx c, int r);
+  ~TimeScope();
+};
 
 }  // namespace paco

@@ -30,26 +30,65 @@ struct ROr {
   static __device__ __forceinline__ T op(T a, T b) { return a | b; }
 };
 
-template <class R>
+// One workgroup per tile; thread t owns VEC consecutive columns of each
+// row of the tile.  Sources are read in batches of 8 so their loads are in
+// flight together, and folded strictly in list (ascending-k) order.
+template <class T, int VEC>
+__device__ __forceinline__ void load_vec(const T* p, T x[VEC]) {
+  if constexpr (VEC == 4) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 q = gload((const u32x4*)p);
+    // copy each lane to a scalar before the bit cast (a bit cast applied to
+    // a vector component expression reads component 0)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t w = q[e];
+      x[e] = __builtin_bit_cast(T, w);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) x[e] = gload(p + e);
+  }
+}
+
+template <class R, int VEC>
 __global__ __launch_bounds__(256) void k_reduce(ProbRef pr, const RedTile* __restrict__ tiles,
                                                 const RedSrc* __restrict__ srcs,
                                                 const typename R::T* __restrict__ ws) {
   using T = typename R::T;
   const RedTile tl = tiles[blockIdx.x];
   const Problem P = uni(get_prob(pr, uni(tl.prob)));
-  const int i0 = uni(tl.i0), j0 = uni(tl.j0);
-  const int w = uni(tl.j1) - j0, h = uni(tl.i1) - i0;
+  const int i0 = uni(tl.i0), i1 = uni(tl.i1), j1 = uni(tl.j1);
   const int s0 = uni(tl.s0), s1 = uni(tl.s1);
   T* C = (T*)P.C;
-  for (int e = threadIdx.x; e < w * h; e += 256) {
-    const int i = i0 + e / w, j = j0 + e % w;
-    T* cp = C + (int64_t)i * P.ldc + j;
-    T v = gload(cp);
-    for (int s = s0; s < s1; ++s) {
-      const RedSrc S = srcs[s];
-      v = R::op(v, gload(ws + S.off + (int64_t)(i - S.r0) * S.ld + (j - S.c0)));
+  for (int j = uni(tl.j0) + (int)threadIdx.x * VEC; j < j1; j += 256 * VEC) {
+    for (int i = i0; i < i1; ++i) {
+      T* cp = C + (int64_t)i * P.ldc + j;
+      T v[VEC];
+      load_vec<T, VEC>(cp, v);
+      auto src_ptr = [&](int s) {
+        const RedSrc S = srcs[s];
+        return ws + S.off + (int64_t)(i - S.r0) * S.ld + (j - S.c0);
+      };
+      int s = s0;
+      for (; s + 8 <= s1; s += 8) {  // eight loads in flight, folded in order
+        T x[8][VEC];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) load_vec<T, VEC>(src_ptr(s + u), x[u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) v[e] = R::op(v[e], x[u][e]);
+      }
+      for (; s < s1; ++s) {
+        T x[VEC];
+        load_vec<T, VEC>(src_ptr(s), x);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[e] = R::op(v[e], x[e]);
+      }
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) gstore(cp + e, v[e]);
     }
-    gstore(cp, v);
   }
 }
 
@@ -63,16 +102,20 @@ __global__ __launch_bounds__(256) void k_fill(T* C, int64_t rows, int64_t cols, 
 }  // namespace
 
 hipError_t launch_reduce(int sr, const ProbRef& pr, const RedTile* tiles, int ntiles,
-                         const RedSrc* srcs, const void* ws, hipStream_t s) {
+                         const RedSrc* srcs, const void* ws, hipStream_t s, int vec) {
   if (ntiles <= 0) return hipSuccess;
   dim3 g(ntiles), b(256);
+#define PACO_RED(R, T)                                                                   \
+  if (vec == 4) hipLaunchKernelGGL((k_reduce<R, 4>), g, b, 0, s, pr, tiles, srcs, (const T*)ws); \
+  else hipLaunchKernelGGL((k_reduce<R, 1>), g, b, 0, s, pr, tiles, srcs, (const T*)ws);
   switch (sr) {
-    case SR_RING: hipLaunchKernelGGL(k_reduce<RSum>, g, b, 0, s, pr, tiles, srcs, (const float*)ws); break;
-    case SR_MINPLUS: hipLaunchKernelGGL(k_reduce<RMin>, g, b, 0, s, pr, tiles, srcs, (const uint32_t*)ws); break;
-    case SR_MAXPLUS: hipLaunchKernelGGL(k_reduce<RMax>, g, b, 0, s, pr, tiles, srcs, (const int32_t*)ws); break;
-    case SR_BOOL: hipLaunchKernelGGL(k_reduce<ROr>, g, b, 0, s, pr, tiles, srcs, (const uint32_t*)ws); break;
+    case SR_RING: PACO_RED(RSum, float); break;
+    case SR_MINPLUS: PACO_RED(RMin, uint32_t); break;
+    case SR_MAXPLUS: PACO_RED(RMax, int32_t); break;
+    case SR_BOOL: PACO_RED(ROr, uint32_t); break;
     default: return hipErrorInvalidValue;
   }
+#undef PACO_RED
   return hipGetLastError();
 }
 

@@ -1,113 +1,120 @@
 // k_ring.hip -- persistent (+,x) ring kernel on gfx950 matrix cores.
 //
-// One workgroup (4 waves, 2 x 2) stands for one processor of the PACO
-// partition and runs its cuboid(s): the C face is swept in BM x BN tiles,
-// the cuboid's k-range folded 32 at a time.  Operands arrive as float32.
-//  FP32   : tiles staged in LDS as float32, v_mfma_f32_16x16x4_f32.
-//  BF16X3 : each element is split while it is written to LDS, hi = bf16(x),
+// One workgroup of WM x WN waves (one or two per SIMD) stands for one
+// processor of the PACO partition and runs its cuboid(s): the C face is
+// swept in BM x BN tiles and the cuboid's k-range folded 32 at a time.
+// Operands arrive as float32.
+//  FP32   : tiles staged in LDS as float32, v_mfma_f32_32x32x2_f32.
+//  BF16X3 : each element is split on its way into LDS, hi = bf16(x),
 //           lo = bf16(x - hi) (round to nearest even; x - hi is exact), and
-//           each 16x16 block takes lo*hi', hi*lo', hi*hi' on
-//           v_mfma_f32_16x16x32_bf16 with float32 accumulation.
+//           each 32x32 block accumulates lo*hi', hi*lo', hi*hi' with
+//           v_mfma_f32_32x32x16_bf16 in float32.
 //  BF16X6 : hi, mid = bf16(x - hi), lo = bf16(x - hi - mid) and the six
 //           products lo*hi', hi*lo', mid*mid', mid*hi', hi*mid', hi*hi'.
-// The split costs no extra HBM pass: global float32 loads for the next step
-// are in flight while the current step runs; the split happens on the way
-// into LDS.  B is stored k-contiguous (transposed) so both operands are read
-// as 8 consecutive k values per lane (one 128-bit LDS read).  Rows of LDS
-// tiles are padded so the 16 rows read by a quarter-wave fall on distinct
-// banks.
+// The split costs no extra HBM pass: the next step's float32 loads are in
+// flight while the current step runs and are split when written to LDS.  B
+// is stored k-contiguous (transposed) so both operands are read as 8
+// consecutive k values per lane with one 128-bit LDS read.  LDS rows are
+// 64 bytes (32 bf16) with the 16-byte chunk index XOR-ed by (row / 4) % 4, so
+// the 16 rows a quarter-wave reads fall on distinct banks without padding.
+// With two waves per SIMD one wave's split and LDS traffic overlaps the
+// other wave's matrix-core work; one wave per SIMD leaves each wave 512
+// registers for a 128 x 128 wave tile.
 //
-// Within a matrix-core instruction each lane group supplies a k-slice; A and
+// Within a matrix-core instruction each half-wave supplies a k-slice; A and
 // B use the same lane-to-k assignment, so every k is paired exactly once.
+#include <type_traits>
+
 #include "kcommon.h"
 #include "kernels.h"
 
 namespace paco {
 namespace {
 
-constexpr int kThreads = 256;
 constexpr int kBK = 32;
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ uint16_t bf16_bits(__bf16 h) { return __builtin_bit_cast(uint16_t, h); }
-__device__ __forceinline__ float bf16_to_f32(__bf16 h) {
-  return __builtin_bit_cast(float, (uint32_t)bf16_bits(h) << 16);
+// Two float32 values -> packed bf16 (round to nearest even), element 0 low.
+__device__ __forceinline__ uint32_t cvt2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
 }
 
-// Split 4 float32 values into NS bf16 parts; part p of value j goes to
-// out[p] bits [16j, 16j+16).
+// Split 4 float32 values into NS packed bf16 parts (4 x 16 bits each).
 template <int NS>
-__device__ __forceinline__ void split4(const float v[4], uint64_t out[NS]) {
+__device__ __forceinline__ void split4(float x0, float x1, float x2, float x3, u32x2 out[NS]) {
 #pragma unroll
-  for (int p = 0; p < NS; ++p) out[p] = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    float r = v[j];
-#pragma unroll
-    for (int p = 0; p < NS; ++p) {
-      __bf16 h = (__bf16)r;
-      out[p] |= (uint64_t)bf16_bits(h) << (16 * j);
-      if (p + 1 < NS) r = r - bf16_to_f32(h);
+  for (int p = 0; p < NS; ++p) {
+    const uint32_t h01 = cvt2(x0, x1), h23 = cvt2(x2, x3);
+    out[p] = (u32x2){h01, h23};
+    if (p + 1 < NS) {
+      x0 -= __builtin_bit_cast(float, h01 << 16);
+      x1 -= __builtin_bit_cast(float, h01 & 0xffff0000u);
+      x2 -= __builtin_bit_cast(float, h23 << 16);
+      x3 -= __builtin_bit_cast(float, h23 & 0xffff0000u);
     }
   }
 }
 
-__device__ __forceinline__ f32x4 mfma_bf16(const bf16x8& a, const bf16x8& b, const f32x4& c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+__device__ __forceinline__ f32x16 mfma_bf16(const bf16x8& a, const bf16x8& b, const f32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ f32x4 mfma_f32(float a, float b, const f32x4& c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+__device__ __forceinline__ f32x16 mfma_f32(float a, float b, const f32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
-// Loads a float32 value range through a buffer resource: VEC issues one
-// 128-bit load (16-byte aligned data), otherwise four 32-bit loads.
 template <bool VEC>
-__device__ __forceinline__ void load4(const __amdgpu_buffer_rsrc_t& r, int voff, int soff, float v[4]) {
+__device__ __forceinline__ f32x4 load4(const __amdgpu_buffer_rsrc_t& r, int voff, int soff) {
   if constexpr (VEC) {
-    f32x4 x = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
-    v[0] = x[0]; v[1] = x[1]; v[2] = x[2]; v[3] = x[3];
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
   } else {
+    f32x4 v;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       v[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff + 4 * j, soff, 0));
+    return v;
   }
 }
 
-template <int PREC, int BM, int BN, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_ring(ProbRef pr, const WorkItem* __restrict__ items,
+// Byte offset in an LDS operand tile of 16-byte chunk `c` of row `r`.
+// bf16 rows: 4 chunks (64 B); float rows: 8 chunks (128 B).
+template <bool F32>
+__device__ __forceinline__ int lds_off(int r, int c) {
+  if constexpr (F32) return r * 128 + ((c ^ ((r >> 1) & 7)) << 4);
+  else return r * 64 + ((c ^ ((r >> 2) & 3)) << 4);
+}
+
+template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
+__global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkItem* __restrict__ items,
                                                     const int32_t* __restrict__ wg_off, int nwg, int xcd,
                                                     float* __restrict__ ws) {
-  constexpr int NS = PREC == PREC_FP32 ? 1 : (PREC == PREC_BF16X3 ? 2 : 3);
   constexpr bool F32 = PREC == PREC_FP32;
-  constexpr int WTM = BM / 2, WTN = BN / 2;      // wave tile
-  constexpr int FM = WTM / 16, FN = WTN / 16;    // 16x16 blocks per wave
-  // LDS row lengths (elements): bf16 rows of 32 + 8 pad, float rows 32 + 4.
-  constexpr int LH = kBK + 8, LF = kBK + 4;
-  constexpr int A_UNITS = BM * (kBK / 4);                    // (row, k-quad)
-  constexpr int B_UNITS = (kBK / 4) * (BN / 4);              // (k-quad, n-quad)
-  constexpr int A_PER = A_UNITS / kThreads, B_PER = (B_UNITS + kThreads - 1) / kThreads;
-  static_assert(A_UNITS % kThreads == 0, "load split");
-  static_assert(B_UNITS % kThreads == 0 || B_UNITS < kThreads, "load split");
-
-  // bf16 parts: [part][buf][row][LH]; float: [buf][row][LF]
-  constexpr int A_H = F32 ? 0 : NS * 2 * BM * LH, B_H = F32 ? 0 : NS * 2 * BN * LH;
-  constexpr int A_F = F32 ? 2 * BM * LF : 0, B_F = F32 ? 2 * BN * LF : 0;
-  __shared__ __align__(16) uint16_t sh_h[(A_H + B_H) > 0 ? (A_H + B_H) : 8];
-  __shared__ __align__(16) float sh_f[(A_F + B_F) > 0 ? (A_F + B_F) : 4];
-  uint16_t* Ah = sh_h;
-  uint16_t* Bh = sh_h + A_H;
-  float* Af = sh_f;
-  float* Bf = sh_f + A_F;
+  constexpr int NS = F32 ? 1 : (PREC == PREC_BF16X3 ? 2 : 3);
+  constexpr int kThreads = 64 * WM * WN;
+  constexpr int WTM = BM / WM, WTN = BN / WN;    // wave tile (waves WM x WN)
+  constexpr int FM = WTM / 32, FN = WTN / 32;    // 32x32 blocks per wave
+  static_assert(FM >= 1 && FN >= 1, "tile");
+  constexpr int ROWB = F32 ? 128 : 64;           // LDS bytes per operand row per part
+  constexpr int A_BYTES = NS * BM * ROWB, B_BYTES = NS * BN * ROWB;   // one buffer
+  constexpr int A_UNITS = BM * (kBK / 4);                  // (row, k-quad)
+  constexpr int B_UNITS = (kBK / 4) * (BN / 4);            // (k-quad, n-quad)
+  constexpr int A_PER = A_UNITS / kThreads;
+  constexpr int B_PER = (B_UNITS + kThreads - 1) / kThreads;
+  static_assert(A_UNITS % kThreads == 0, "A load split");
+  static_assert(B_UNITS % kThreads == 0 || B_UNITS < kThreads, "B load split");
+  __shared__ __align__(16) char lds[2 * (A_BYTES + B_BYTES)];
 
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wr = (wave >> 1) * WTM, wc = (wave & 1) * WTN;   // wave origin in tile
-  const int lr = lane & 15, lg = lane >> 4;                   // row/col in block, k-group
+  const int wr = (wave / WN) * WTM, wc = (wave % WN) * WTN;   // wave origin in the tile
+  const int l32 = lane & 31, lh = lane >> 5;                   // row/col in block, k-half
   const int q = remap_wg(blockIdx.x, nwg, xcd);
   const int it1 = wg_off[q + 1];
-  int buf = 0;
 
   for (int it = wg_off[q]; it < it1; ++it) {
     const WorkItem W = uni(items[it]);
@@ -116,171 +123,221 @@ __global__ __launch_bounds__(kThreads) void k_ring(ProbRef pr, const WorkItem* _
     const float* B = (const float*)P.B;
     for (int i0 = W.n0; i0 < W.n1; i0 += BM) {
       for (int j0 = W.m0; j0 < W.m1; j0 += BN) {
-        f32x4 acc[FM][FN];
+        f32x16 acc[FM][FN];
 #pragma unroll
         for (int a = 0; a < FM; ++a)
 #pragma unroll
-          for (int b = 0; b < FN; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+          for (int b = 0; b < FN; ++b)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[a][b][e] = 0.f;
 
         const auto a_rsrc = make_rsrc(A + (int64_t)i0 * P.lda, P.n - i0, P.lda, P.k);
-        // A unit u = t + s*256: row u / 8, k-quad u % 8 (row step 32 per s)
-        const int a_row = t / (kBK / 4), a_kq = t % (kBK / 4);
-        int a_voff = (a_row * (int)P.lda + W.k0 + 4 * a_kq) * 4;
-        const int a_soff = (kThreads / (kBK / 4)) * (int)P.lda * 4;
-        // B unit u = t + s*256: n-quad u % (BN/4), k-quad u / (BN/4)
-        float ra[A_PER][4], rb[B_PER][4][4];
-        int a_klim = 0, b_klim = 0;
-        auto load = [&](int kk) {
-          a_klim = W.k1 - kk;
+        // A unit u = t + s*kThreads: row u / 8, k-quad t % 8
+        const int a_row = t >> 3, a_kq = t & 7;
+        const int a_voff0 = (a_row * (int)P.lda + 4 * a_kq) * 4;
+        const int a_soff = (kThreads / 8) * (int)P.lda * 4;
+        // B unit u = t + s*kThreads: n-quad u % (BN/4), k-quad u / (BN/4)
+        // Two register sets: the global loads of step s+2 are in flight while
+        // step s+1 (loaded earlier) is split into LDS and step s is computed.
+        struct Regs {
+          f32x4 a[A_PER];
+          f32x4 b[B_PER][4];
+          int klim;
+        };
+        Regs R0, R1;
+        auto load = [&](Regs& R, int kk) {
+          R.klim = W.k1 - kk;
 #pragma unroll
-          for (int s = 0; s < A_PER; ++s) load4<VEC>(a_rsrc, a_voff, s * a_soff, ra[s]);
-          a_voff += kBK * 4;
+          for (int s = 0; s < A_PER; ++s) R.a[s] = load4<VEC>(a_rsrc, a_voff0 + kk * 4, s * a_soff);
           const auto b_rsrc = make_rsrc(B + (int64_t)kk * P.ldb, P.k - kk, P.ldb, P.m);
-          b_klim = W.k1 - kk;
 #pragma unroll
           for (int s = 0; s < B_PER; ++s) {
             const int u = t + s * kThreads;
-            if (u >= B_UNITS) break;
-            const int nq = u % (BN / 4), kq = u / (BN / 4);
-            const int voff = ((4 * kq) * (int)P.ldb + j0 + 4 * nq) * 4;
+            if (u < B_UNITS) {
+              const int nq = u % (BN / 4), kq = u / (BN / 4);
+              const int voff = ((4 * kq) * (int)P.ldb + j0 + 4 * nq) * 4;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) load4<VEC>(b_rsrc, voff, r * (int)P.ldb * 4, rb[s][r]);
+              for (int r = 0; r < 4; ++r) R.b[s][r] = load4<VEC>(b_rsrc, voff, r * (int)P.ldb * 4);
+            }
           }
         };
-        auto store = [&]() {
-          // A: zero k beyond the piece; rows beyond the piece are discarded
+        auto store = [&](const Regs& R, int bsel) {
+          char* As = lds + bsel * (A_BYTES + B_BYTES);
+          char* Bs = As + A_BYTES;
+          // k beyond the piece is zeroed; rows beyond it are discarded later
 #pragma unroll
           for (int s = 0; s < A_PER; ++s) {
-            const int row = a_row + s * (kThreads / (kBK / 4));
-            float v[4];
+            const int row = a_row + s * (kThreads / 8);
+            f32x4 v = R.a[s];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = (4 * a_kq + j < a_klim) ? ra[s][j] : 0.f;
+            for (int j = 0; j < 4; ++j)
+              if (4 * a_kq + j >= R.klim) v[j] = 0.f;
             if constexpr (F32) {
-              *(f32x4*)&Af[(buf * BM + row) * LF + 4 * a_kq] = f32x4{v[0], v[1], v[2], v[3]};
+              *(f32x4*)(As + lds_off<true>(row, a_kq)) = v;
             } else {
-              uint64_t parts[NS];
-              split4<NS>(v, parts);
+              u32x2 parts[NS];
+              split4<NS>(v[0], v[1], v[2], v[3], parts);
 #pragma unroll
               for (int p = 0; p < NS; ++p)
-                *(uint64_t*)&Ah[((p * 2 + buf) * BM + row) * LH + 4 * a_kq] = parts[p];
+                *(u32x2*)(As + p * BM * ROWB + lds_off<false>(row, a_kq >> 1) + (a_kq & 1) * 8) = parts[p];
             }
           }
 #pragma unroll
           for (int s = 0; s < B_PER; ++s) {
             const int u = t + s * kThreads;
-            if (u >= B_UNITS) break;
-            const int nq = u % (BN / 4), kq = u / (BN / 4);
+            if (u < B_UNITS) {
+              const int nq = u % (BN / 4), kq = u / (BN / 4);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              float v[4];
+              for (int c = 0; c < 4; ++c) {
+                float v[4];
 #pragma unroll
-              for (int r = 0; r < 4; ++r) v[r] = (4 * kq + r < b_klim) ? rb[s][r][c] : 0.f;
-              const int n = 4 * nq + c;
-              if constexpr (F32) {
-                *(f32x4*)&Bf[(buf * BN + n) * LF + 4 * kq] = f32x4{v[0], v[1], v[2], v[3]};
-              } else {
-                uint64_t parts[NS];
-                split4<NS>(v, parts);
+                for (int r = 0; r < 4; ++r) v[r] = (4 * kq + r < R.klim) ? R.b[s][r][c] : 0.f;
+                const int n = 4 * nq + c;
+                if constexpr (F32) {
+                  *(f32x4*)(Bs + lds_off<true>(n, kq)) = (f32x4){v[0], v[1], v[2], v[3]};
+                } else {
+                  u32x2 parts[NS];
+                  split4<NS>(v[0], v[1], v[2], v[3], parts);
 #pragma unroll
-                for (int p = 0; p < NS; ++p)
-                  *(uint64_t*)&Bh[((p * 2 + buf) * BN + n) * LH + 4 * kq] = parts[p];
+                  for (int p = 0; p < NS; ++p)
+                    *(u32x2*)(Bs + p * BN * ROWB + lds_off<false>(n, kq >> 1) + (kq & 1) * 8) = parts[p];
+                }
               }
             }
           }
         };
-
-        if (W.k0 < W.k1) load(W.k0);
-        for (int kk = W.k0; kk < W.k1; kk += kBK) {
-          store();
-          __syncthreads();
-          if (kk + kBK < W.k1) load(kk + kBK);
+        // One step: read all fragments of buffer bsel, then the matrix-core
+        // work, with the split of the next step (into the other buffer)
+        // available to the scheduler in between.
+        auto step = [&](int bsel, const Regs* next) {
+          const char* As = lds + bsel * (A_BYTES + B_BYTES);
+          const char* Bs = As + A_BYTES;
           if constexpr (F32) {
+            f32x4 fa[4][FM], fb[4][FN];
 #pragma unroll
-            for (int kh = 0; kh < kBK / 16; ++kh) {
-              f32x4 fa[FM], fb[FN];
+            for (int s = 0; s < 4; ++s) {
 #pragma unroll
-              for (int a = 0; a < FM; ++a)
-                fa[a] = *(const f32x4*)&Af[(buf * BM + wr + a * 16 + lr) * LF + kh * 16 + 4 * lg];
+              for (int a = 0; a < FM; ++a) fa[s][a] = *(const f32x4*)(As + lds_off<true>(wr + a * 32 + l32, 2 * s + lh));
 #pragma unroll
-              for (int b = 0; b < FN; ++b)
-                fb[b] = *(const f32x4*)&Bf[(buf * BN + wc + b * 16 + lr) * LF + kh * 16 + 4 * lg];
+              for (int b = 0; b < FN; ++b) fb[s][b] = *(const f32x4*)(Bs + lds_off<true>(wc + b * 32 + l32, 2 * s + lh));
+            }
+            if (next) store(*next, bsel ^ 1);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
               for (int a = 0; a < FM; ++a)
 #pragma unroll
                 for (int b = 0; b < FN; ++b)
 #pragma unroll
-                  for (int j = 0; j < 4; ++j) acc[a][b] = mfma_f32(fa[a][j], fb[b][j], acc[a][b]);
-            }
+                  for (int j = 0; j < 4; ++j) acc[a][b] = mfma_f32(fa[s][a][j], fb[s][b][j], acc[a][b]);
           } else {
-            bf16x8 fa[FM][NS], fb[FN][NS];
+            bf16x8 fa[2][FM][NS], fb[2][FN][NS];
 #pragma unroll
-            for (int a = 0; a < FM; ++a)
+            for (int kh = 0; kh < 2; ++kh) {
 #pragma unroll
-              for (int p = 0; p < NS; ++p)
-                fa[a][p] = *(const bf16x8*)&Ah[((p * 2 + buf) * BM + wr + a * 16 + lr) * LH + 8 * lg];
+              for (int a = 0; a < FM; ++a)
 #pragma unroll
-            for (int b = 0; b < FN; ++b)
+                for (int p = 0; p < NS; ++p)
+                  fa[kh][a][p] = *(const bf16x8*)(As + p * BM * ROWB + lds_off<false>(wr + a * 32 + l32, 2 * kh + lh));
 #pragma unroll
-              for (int p = 0; p < NS; ++p)
-                fb[b][p] = *(const bf16x8*)&Bh[((p * 2 + buf) * BN + wc + b * 16 + lr) * LH + 8 * lg];
+              for (int b = 0; b < FN; ++b)
 #pragma unroll
-            for (int a = 0; a < FM; ++a)
+                for (int p = 0; p < NS; ++p)
+                  fb[kh][b][p] = *(const bf16x8*)(Bs + p * BN * ROWB + lds_off<false>(wc + b * 32 + l32, 2 * kh + lh));
+            }
+            if (next) store(*next, bsel ^ 1);
 #pragma unroll
-              for (int b = 0; b < FN; ++b) {
-                f32x4 c = acc[a][b];
-                if constexpr (NS == 2) {
-                  c = mfma_bf16(fa[a][1], fb[b][0], c);
-                  c = mfma_bf16(fa[a][0], fb[b][1], c);
-                  c = mfma_bf16(fa[a][0], fb[b][0], c);
-                } else {
-                  c = mfma_bf16(fa[a][2], fb[b][0], c);
-                  c = mfma_bf16(fa[a][0], fb[b][2], c);
-                  c = mfma_bf16(fa[a][1], fb[b][1], c);
-                  c = mfma_bf16(fa[a][1], fb[b][0], c);
-                  c = mfma_bf16(fa[a][0], fb[b][1], c);
-                  c = mfma_bf16(fa[a][0], fb[b][0], c);
+            for (int kh = 0; kh < 2; ++kh)
+#pragma unroll
+              for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b) {
+                  f32x16 c = acc[a][b];
+                  if constexpr (NS == 2) {
+                    c = mfma_bf16(fa[kh][a][1], fb[kh][b][0], c);
+                    c = mfma_bf16(fa[kh][a][0], fb[kh][b][1], c);
+                    c = mfma_bf16(fa[kh][a][0], fb[kh][b][0], c);
+                  } else {
+                    c = mfma_bf16(fa[kh][a][2], fb[kh][b][0], c);
+                    c = mfma_bf16(fa[kh][a][0], fb[kh][b][2], c);
+                    c = mfma_bf16(fa[kh][a][1], fb[kh][b][1], c);
+                    c = mfma_bf16(fa[kh][a][1], fb[kh][b][0], c);
+                    c = mfma_bf16(fa[kh][a][0], fb[kh][b][1], c);
+                    c = mfma_bf16(fa[kh][a][0], fb[kh][b][0], c);
+                  }
+                  acc[a][b] = c;
                 }
-                acc[a][b] = c;
-              }
           }
-          buf ^= 1;
+        };
+
+        // prologue: step 0 into buffer 0, step 1 in flight
+        if (W.k0 < W.k1) {
+          load(R0, W.k0);
+          store(R0, 0);
+          __syncthreads();
+          if (W.k0 + kBK < W.k1) load(R1, W.k0 + kBK);
+        }
+        // steps s (buffer s % 2); R1 holds step s+1 on even s, R0 on odd s
+        for (int kk = W.k0; kk < W.k1; kk += 2 * kBK) {
+          const bool has1 = kk + kBK < W.k1, has2 = kk + 2 * kBK < W.k1;
+          if (has2) load(R0, kk + 2 * kBK);
+          step(0, has1 ? &R1 : nullptr);
+          __syncthreads();
+          if (!has1) break;
+          if (kk + 3 * kBK < W.k1) load(R1, kk + 3 * kBK);
+          step(1, has2 ? &R0 : nullptr);
+          __syncthreads();
         }
 
-        // epilogue: lane holds column lr, rows 4*lg + r of each 16x16 block
-        const int64_t tld = W.m1 - W.m0;
+        // epilogue: lane holds column l32 of each 32x32 block, value 4g + r
+        // in row 8g + 4*lh + r.  Stores go through a buffer resource that
+        // ends at the piece's last row, so rows past the piece are dropped by
+        // the range check; columns past it are skipped per block.
+        float* obase;
+        int64_t old;
+        if (W.out_off < 0) {
+          obase = (float*)P.C + (int64_t)i0 * P.ldc;
+          old = P.ldc;
+        } else {
+          old = W.m1 - W.m0;
+          obase = ws + W.out_off + (int64_t)(i0 - W.n0) * old - W.m0;
+        }
+        const auto o_rsrc = make_rsrc(obase, W.n1 - i0, old, W.m1);
+        const bool accum = W.out_off < 0 && P.accumulate;
+        auto epilogue = [&](auto accum_c) {
+          constexpr bool ACC = decltype(accum_c)::value;
 #pragma unroll
-        for (int a = 0; a < FM; ++a)
+          for (int a = 0; a < FM; ++a)
 #pragma unroll
-          for (int b = 0; b < FN; ++b) {
-            const int c = j0 + wc + b * 16 + lr;
-            if (c >= W.m1) continue;
+            for (int b = 0; b < FN; ++b) {
+              const int c = j0 + wc + b * 32 + l32;
+              if (c >= W.m1) continue;
+              const int voff = ((wr + a * 32 + 4 * lh) * (int)old + c) * 4;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int row = i0 + wr + a * 16 + 4 * lg + r;
-              if (row >= W.n1) continue;
-              float v = acc[a][b][r];
-              if (W.out_off < 0) {
-                float* cp = (float*)P.C + (int64_t)row * P.ldc + c;
-                if (P.accumulate) v = gload(cp) + v;
-                gstore(cp, v);
-              } else {
-                gstore(ws + W.out_off + (int64_t)(row - W.n0) * tld + (c - W.m0), v);
+              for (int e = 0; e < 16; ++e) {
+                const int soff = (8 * (e >> 2) + (e & 3)) * (int)old * 4;
+                float v = acc[a][b][e];
+                if constexpr (ACC)
+                  v += __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(o_rsrc, voff, soff, 0));
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), o_rsrc, voff, soff, 0);
               }
             }
-          }
+        };
+        if (accum) epilogue(std::true_type{});
+        else epilogue(std::false_type{});
       }
     }
   }
 }
 
-template <int PREC, int BM, int BN>
+template <int PREC, int BM, int BN, int WM, int WN>
 hipError_t launch_shape(bool vec, const ProbRef& pr, const WorkItem* items, const int32_t* wg_off, int nwg,
                         int xcd, void* ws, hipStream_t s) {
-  dim3 g(nwg), b(kThreads);
+  dim3 g(nwg), b(64 * WM * WN);
   if (vec)
-    hipLaunchKernelGGL((k_ring<PREC, BM, BN, true>), g, b, 0, s, pr, items, wg_off, nwg, xcd, (float*)ws);
+    hipLaunchKernelGGL((k_ring<PREC, BM, BN, WM, WN, true>), g, b, 0, s, pr, items, wg_off, nwg, xcd, (float*)ws);
   else
-    hipLaunchKernelGGL((k_ring<PREC, BM, BN, false>), g, b, 0, s, pr, items, wg_off, nwg, xcd, (float*)ws);
+    hipLaunchKernelGGL((k_ring<PREC, BM, BN, WM, WN, false>), g, b, 0, s, pr, items, wg_off, nwg, xcd, (float*)ws);
   return hipGetLastError();
 }
 
@@ -288,13 +345,10 @@ template <int PREC>
 hipError_t launch_prec(int tile, bool vec, const ProbRef& pr, const WorkItem* items, const int32_t* wg_off,
                        int nwg, int xcd, void* ws, hipStream_t s) {
   switch (tile) {
-    case RING_T128x128: return launch_shape<PREC, 128, 128>(vec, pr, items, wg_off, nwg, xcd, ws, s);
-    case RING_T64x64: return launch_shape<PREC, 64, 64>(vec, pr, items, wg_off, nwg, xcd, ws, s);
-    case RING_T256x128:
-      // three bf16 parts of a 256 x 128 tile do not fit the 160 KiB of LDS
-      if constexpr (PREC != PREC_BF16X6)
-        return launch_shape<PREC, 256, 128>(vec, pr, items, wg_off, nwg, xcd, ws, s);
-      break;
+    case RING_T256x128: return launch_shape<PREC, 256, 128, 4, 2>(vec, pr, items, wg_off, nwg, xcd, ws, s);
+    case RING_T128x128: return launch_shape<PREC, 128, 128, 4, 2>(vec, pr, items, wg_off, nwg, xcd, ws, s);
+    case RING_T128x64: return launch_shape<PREC, 128, 64, 4, 2>(vec, pr, items, wg_off, nwg, xcd, ws, s);
+    case RING_T128x128W4: return launch_shape<PREC, 128, 128, 2, 2>(vec, pr, items, wg_off, nwg, xcd, ws, s);
   }
   return hipErrorInvalidValue;
 }
@@ -304,9 +358,10 @@ hipError_t launch_prec(int tile, bool vec, const ProbRef& pr, const WorkItem* it
 RingTileShape ring_tile_shape(int tile, int prec) {
   (void)prec;
   switch (tile) {
-    case RING_T128x128: return {128, 128, kBK};
-    case RING_T64x64: return {64, 64, kBK};
     case RING_T256x128: return {256, 128, kBK};
+    case RING_T128x128: return {128, 128, kBK};
+    case RING_T128x64: return {128, 64, kBK};
+    case RING_T128x128W4: return {128, 128, kBK};
   }
   return {0, 0, 0};
 }

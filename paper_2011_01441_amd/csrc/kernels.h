@@ -28,15 +28,19 @@ hipError_t launch_semiring_bool(int tile, const ProbRef& pr, const WorkItem* ite
                                 hipStream_t s);
 
 // (+,x) ring kernel on matrix cores.
-enum RingTile : int { RING_T128x128 = 0, RING_T64x64 = 1, RING_T256x128 = 2 };
+// Tile shapes of the ring kernel (32 k per step): 8 waves (4 x 2) unless
+// marked W4 (4 waves, 2 x 2).
+enum RingTile : int { RING_T256x128 = 0, RING_T128x128 = 1, RING_T128x64 = 2, RING_T128x128W4 = 3 };
 struct RingTileShape { int tm, tn, bk; };
 RingTileShape ring_tile_shape(int tile, int prec);
 hipError_t launch_ring(int prec, int tile, const ProbRef& pr, const WorkItem* items,
                        const int32_t* wg_off, int nwg, int xcd_remap, void* ws, hipStream_t s);
 
-// Fold temporary faces into C (ascending k), one workgroup per tile.
+// Fold temporary faces into C (ascending k), one workgroup per tile; a tile
+// spans at most 256 * vec columns.  vec = 4 needs every C row segment and
+// source face 16-byte aligned (HostPlan::red_vec).
 hipError_t launch_reduce(int sr, const ProbRef& pr, const RedTile* tiles, int ntiles,
-                         const RedSrc* srcs, const void* ws, hipStream_t s);
+                         const RedSrc* srcs, const void* ws, hipStream_t s, int vec);
 
 // C = semiring zero (or unchanged when accumulating) for k = 0.
 hipError_t launch_fill_zero(int sr, void* C, int64_t rows, int64_t cols, int64_t ldc,

@@ -16,7 +16,7 @@
 namespace paco {
 
 HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_remap,
-                    const std::vector<ProbGeom>& geom, int64_t temp_base) {
+                    const std::vector<ProbGeom>& geom, int64_t temp_base, int red_vec) {
   HostPlan hp;
   hp.nwg = nwg;
   hp.xcd_remap = xcd_remap && nwg % 8 == 0;
@@ -38,7 +38,8 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
     hp.vmin = hp.n_pieces == 1 ? v : std::min(hp.vmin, v);
     if (p.k0 > 0) {
       off[i] = cur;
-      cur += (p.n1 - p.n0) * (p.m1 - p.m0);
+      // faces start on 16-byte boundaries
+      cur += ((p.n1 - p.n0) * (p.m1 - p.m0) + 3) / 4 * 4;
       ++hp.n_kcuts;
     }
   }
@@ -61,6 +62,13 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
   }
   hp.wg_off[nwg] = (int32_t)hp.items.size();
   if (hp.n_kcuts == 0) return hp;
+  int vec = red_vec == 4 ? 4 : 1;
+  for (size_t i = 0; i < pieces.size() && vec == 4; ++i) {
+    if (off[i] < 0) continue;
+    const Piece& p = pieces[i].pc;
+    if ((p.m1 - p.m0) % 4 || p.m0 % 4 || off[i] % 4) vec = 1;
+  }
+  hp.red_vec = vec;
 
   // reduction cells per problem
   std::map<int, std::vector<int>> temps_of;  // prob -> temp piece indices
@@ -105,10 +113,11 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
           hp.srcs.push_back(s);
         }
         int32_t s1 = (int32_t)hp.srcs.size();
-        // split the cell into tiles of about 4096 elements
+        // split the cell into tiles of at most 256*vec columns and about
+        // 1024 elements (many workgroups: the fold is bandwidth-bound)
         int64_t i0 = rb[r], i1 = rb[r + 1], j0 = cb[c], j1 = cb[c + 1];
-        int64_t cw = std::min<int64_t>(j1 - j0, 1024);
-        int64_t rh = std::max<int64_t>(1, 4096 / cw);
+        int64_t cw = std::min<int64_t>(j1 - j0, 256 * vec);
+        int64_t rh = std::max<int64_t>(1, 1024 / cw);
         for (int64_t ii = i0; ii < i1; ii += rh)
           for (int64_t jj = j0; jj < j1; jj += cw) {
             RedTile t;

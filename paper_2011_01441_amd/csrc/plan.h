@@ -23,6 +23,7 @@ struct HostPlan {
   std::vector<RedTile> tiles;
   std::vector<RedSrc> srcs;
   int64_t temp_elems = 0;          // workspace elements for temporary faces
+  int red_vec = 1;                 // reduction vector width (4 when aligned)
   // statistics over non-empty pieces
   int32_t n_pieces = 0, n_kcuts = 0;
   int64_t vmax = 0, vmin = 0;
@@ -39,7 +40,10 @@ struct TaggedPiece {
 // k0 > 0 writes its own temporary face (allocated after `temp_base`
 // elements); every covered C element then folds its faces in ascending-k
 // order.  `geom` gives each problem's C size (rows, cols in kernel units).
+// `red_vec` 4 asks for 4-wide reduction tiles; the plan falls back to 1
+// unless every face offset, width and column origin is a multiple of 4
+// (the caller checks the alignment of C itself).
 HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_remap,
-                    const std::vector<ProbGeom>& geom, int64_t temp_base = 0);
+                    const std::vector<ProbGeom>& geom, int64_t temp_base = 0, int red_vec = 4);
 
 }  // namespace paco

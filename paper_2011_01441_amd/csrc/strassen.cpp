@@ -133,23 +133,35 @@ extern "C" paco_status paco_strassen_mm(paco_ctx ctx, int64_t n, const float* A,
   float* T = S + nleaf * blk;
   float* M = T + nleaf * blk;
 
-  if ((e = launch_strassen_preadd(levels, n, A, B, S, T, ctx->stream)) != hipSuccess)
-    return hip_fail(ctx, e, "Strassen pre-add");
+  {
+    TimeScope ts(ctx, 2);
+    e = launch_strassen_preadd(levels, n, A, B, S, T, ctx->stream);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "Strassen pre-add");
   ProbRef pr;
   memset(&pr, 0, sizeof pr);
   pr.base.A = S; pr.base.B = T; pr.base.C = M;
   pr.base.lda = pr.base.ldb = pr.base.ldc = h;
   pr.base.n = pr.base.m = pr.base.k = (int32_t)h;
   pr.sA = pr.sB = pr.sC = (int64_t)blk;
-  if ((e = launch_ring(prec, dp->tile, pr, dp->d_items, dp->d_wg_off, dp->h.nwg, dp->h.xcd_remap, ctx->ws,
-                       ctx->stream)) != hipSuccess)
-    return hip_fail(ctx, e, "Strassen leaf launch");
-  if (!dp->h.tiles.empty()) {
-    if ((e = launch_reduce(SR_RING, pr, dp->d_tiles, (int)dp->h.tiles.size(), dp->d_srcs, ctx->ws,
-                           ctx->stream)) != hipSuccess)
-      return hip_fail(ctx, e, "Strassen leaf reduce");
+  {
+    TimeScope ts(ctx, 0);
+    e = launch_ring(prec, dp->tile, pr, dp->d_items, dp->d_wg_off, dp->h.nwg, dp->h.xcd_remap, ctx->ws,
+                    ctx->stream);
   }
-  if ((e = launch_strassen_combine(levels, n, M, C, ctx->stream)) != hipSuccess)
-    return hip_fail(ctx, e, "Strassen combine");
+  if (e != hipSuccess) return hip_fail(ctx, e, "Strassen leaf launch");
+  if (!dp->h.tiles.empty()) {
+    {
+      TimeScope ts(ctx, 1);
+      e = launch_reduce(SR_RING, pr, dp->d_tiles, (int)dp->h.tiles.size(), dp->d_srcs, ctx->ws, ctx->stream,
+                        dp->h.red_vec);
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "Strassen leaf reduce");
+  }
+  {
+    TimeScope ts(ctx, 2);
+    e = launch_strassen_combine(levels, n, M, C, ctx->stream);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "Strassen combine");
   return PACO_OK;
 }

@@ -124,10 +124,9 @@ int choose_bool_tile(const std::vector<Piece>& pcs) {
 }
 
 int choose_ring_tile(const std::vector<Piece>& pcs, int prec) {
-  const int cand[3] = {RING_T256x128, RING_T128x128, RING_T64x64};
-  const double eff[3] = {1.0, 1.1, 1.6};
-  const int nc = prec == PREC_BF16X6 ? 2 : 3;
-  return choose_tile(pcs, cand + (3 - nc), eff + (3 - nc), nc, [prec](int t, int& tm, int& tn) {
+  const int cand[3] = {RING_T256x128, RING_T128x128, RING_T128x64};
+  const double eff[3] = {1.0, 1.12, 1.5};
+  return choose_tile(pcs, cand, eff, 3, [prec](int t, int& tm, int& tn) {
     RingTileShape s = ring_tile_shape(t, prec);
     tm = s.tm;
     tn = s.tn;

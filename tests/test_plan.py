@@ -1,0 +1,100 @@
+"""Host logic: the work plan libpaco launches, replayed on the CPU.
+
+paco_plan_export returns the exact work items and reduction tiles a call
+launches.  Replaying them with numpy -- each item folds its k-range into C
+or into its temporary face, then every reduction tile folds its faces in
+order -- must give the oracle's result, and the plan must cover every
+(i, j, l) exactly once with disjoint writes (the paper's no-data-race
+model)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+P = pytest.importorskip("paper_2011_01441_amd")
+INF, NEG_INF = oracle.INF, oracle.NEG_INF
+
+
+def _partial(sr, A, B, it):
+    _, n0, n1, m0, m1, k0, k1, _ = it
+    a = A[n0:n1, k0:k1].astype(np.int64)
+    b = B[k0:k1, m0:m1].astype(np.int64)
+    if sr == "minplus":
+        return np.minimum(np.min(a[:, :, None] + b[None, :, :], axis=1), INF)
+    if sr == "maxplus":
+        s = a[:, :, None] + b[None, :, :]
+        s = np.where((a[:, :, None] == NEG_INF) | (b[None, :, :] == NEG_INF), NEG_INF, s)
+        return np.max(s, axis=1)
+    return a @ b    # ring on small integers
+
+
+def _fold(sr, x, y):
+    return {"minplus": np.minimum, "maxplus": np.maximum}.get(sr, np.add)(x, y)
+
+
+def replay(sr, A, B, n, m, k, **kw):
+    items, wg, tiles, srcs, info = P.plan_export(n, m, k, sr, **kw)
+    C = np.full((n, m), 12345678, np.int64)
+    ws = np.full(max(info["temp_elems"], 1), -7777, np.int64)
+    written = np.zeros((n, m), np.int64)
+    kcover = np.zeros((n, m), np.int64)
+    face_owner = np.full(ws.shape, -1, np.int64)
+    for q in range(info["n_wg"]):
+        for idx in range(wg[q], wg[q + 1]):
+            it = items[idx]
+            _, n0, n1, m0, m1, k0, k1, off = it
+            part = _partial(sr, A, B, it)
+            kcover[n0:n1, m0:m1] += k1 - k0
+            if off < 0:
+                C[n0:n1, m0:m1] = part
+                written[n0:n1, m0:m1] += 1
+            else:
+                sz = (n1 - n0) * (m1 - m0)
+                assert (face_owner[off:off + sz] < 0).all(), "temporary faces overlap"
+                face_owner[off:off + sz] = idx
+                ws[off:off + sz] = part.reshape(-1)
+    assert (written == 1).all(), "each C element must be written by exactly one piece"
+    assert (kcover == k).all(), "each (i, j) must see every l exactly once"
+    for t in tiles:
+        _, i0, i1, j0, j1, s0, s1 = t
+        for s in range(s0, s1):
+            off, ld, r0, c0 = srcs[s]
+            rr = np.arange(i0, i1)[:, None] - r0
+            cc = np.arange(j0, j1)[None, :] - c0
+            C[i0:i1, j0:j1] = _fold(sr, C[i0:i1, j0:j1], ws[off + rr * ld + cc])
+    return C, info
+
+
+@pytest.mark.parametrize("p,part,sk", [(256, "paco", 0), (1, "paco", 0), (3, "paco", 0),
+                                       (257, "paco", 0), (7, "grid", 3), (256, "grid", 0)])
+def test_minplus_config0_plan_replay(p, part, sk):
+    A, B = workloads.minplus_operands(384, 256, 320, seed=0)
+    C, info = replay("minplus", A, B, 384, 256, 320, part=part, p=p, split_k=sk)
+    np.testing.assert_array_equal(C, oracle.minplus(A, B))
+
+
+@pytest.mark.parametrize("n,m,k", [(97, 130, 75), (33, 250, 64), (5, 3, 200)])
+def test_maxplus_plan_replay(n, m, k):
+    A, B = workloads.maxplus_operands(n, m, k, seed=3)
+    A[2, :] = NEG_INF
+    C, _ = replay("maxplus", A, B, n, m, k, p=64)
+    np.testing.assert_array_equal(C, oracle.maxplus(A, B))
+
+
+@pytest.mark.parametrize("n,m,k,p", [(64, 48, 2048, 64), (70, 90, 300, 256), (256, 256, 256, 7)])
+def test_ring_plan_replay_small_integers(n, m, k, p):
+    A, B = workloads.small_int_operands(n, m, k, seed=1)
+    C, info = replay("ring", A.astype(np.int64), B.astype(np.int64), n, m, k, p=p)
+    np.testing.assert_array_equal(C, oracle.ring_i64(A.astype(np.int64), B.astype(np.int64)))
+
+
+def test_plan_sizes_match_paper_shapes():
+    # long k: (2048, 1024, 65536) on 256 processors -> 512 x 1024 x 1024 pieces,
+    # k cut 64-way: 252 temporary faces (4 n-blocks x 63)
+    items, wg, tiles, srcs, info = P.plan_export(2048, 1024, 65536, "ring", p=256,
+                                                 precision="bf16x3")
+    ext = items[:, [2, 4, 6]] - items[:, [1, 3, 5]]
+    assert (ext == [512, 1024, 1024]).all()
+    assert (items[:, 7] >= 0).sum() == 252
+    assert info["xcd_remap"] == 1 and info["n_wg"] == 256
