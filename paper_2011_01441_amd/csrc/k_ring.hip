@@ -82,11 +82,17 @@ __device__ __forceinline__ f32x4 load4(const __amdgpu_buffer_rsrc_t& r, int voff
 }
 
 // Byte offset in an LDS operand tile of 16-byte chunk `c` of row `r`.
-// bf16 rows: 4 chunks (64 B); float rows: 8 chunks (128 B).
-template <bool F32>
+// bf16 rows: 4 chunks (64 B); float rows: 8 chunks (128 B).  For B tiles
+// (PERM) the row is also rotated within its group of four by (r / 4) % 4:
+// the transposing store writes rows 4q + c of many n-quads q at once, which
+// would otherwise all hit the same banks; reads of 16 consecutive rows stay
+// on 16 distinct bank groups either way.
+template <bool F32, bool PERM = false>
 __device__ __forceinline__ int lds_off(int r, int c) {
-  if constexpr (F32) return r * 128 + ((c ^ ((r >> 1) & 7)) << 4);
-  else return r * 64 + ((c ^ ((r >> 2) & 3)) << 4);
+  const int g = (r >> 2) & 3;
+  const int pr = PERM ? ((r & ~3) | (((r & 3) + g) & 3)) : r;
+  if constexpr (F32) return pr * 128 + ((c ^ ((r >> 1) & 7)) << 4);
+  else return pr * 64 + ((c ^ g) << 4);
 }
 
 template <int PREC, int BM, int BN, int WM, int WN, bool VEC>
@@ -136,42 +142,36 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
         const int a_row = t >> 3, a_kq = t & 7;
         const int a_voff0 = (a_row * (int)P.lda + 4 * a_kq) * 4;
         const int a_soff = (kThreads / 8) * (int)P.lda * 4;
-        // B unit u = t + s*kThreads: n-quad u % (BN/4), k-quad u / (BN/4)
-        // Two register sets: the global loads of step s+2 are in flight while
-        // step s+1 (loaded earlier) is split into LDS and step s is computed.
-        struct Regs {
-          f32x4 a[A_PER];
-          f32x4 b[B_PER][4];
-          int klim;
-        };
-        Regs R0, R1;
-        auto load = [&](Regs& R, int kk) {
-          R.klim = W.k1 - kk;
+        // B unit u = t + s*kThreads: k-quad u % 8, n-quad u / 8
+        f32x4 ra[A_PER], rb[B_PER][4];
+        int klim = 0;
+        auto load = [&](int kk) {
+          klim = W.k1 - kk;
 #pragma unroll
-          for (int s = 0; s < A_PER; ++s) R.a[s] = load4<VEC>(a_rsrc, a_voff0 + kk * 4, s * a_soff);
+          for (int s = 0; s < A_PER; ++s) ra[s] = load4<VEC>(a_rsrc, a_voff0 + kk * 4, s * a_soff);
           const auto b_rsrc = make_rsrc(B + (int64_t)kk * P.ldb, P.k - kk, P.ldb, P.m);
 #pragma unroll
           for (int s = 0; s < B_PER; ++s) {
             const int u = t + s * kThreads;
             if (u < B_UNITS) {
-              const int nq = u % (BN / 4), kq = u / (BN / 4);
+              const int kq = u & 7, nq = u >> 3;
               const int voff = ((4 * kq) * (int)P.ldb + j0 + 4 * nq) * 4;
 #pragma unroll
-              for (int r = 0; r < 4; ++r) R.b[s][r] = load4<VEC>(b_rsrc, voff, r * (int)P.ldb * 4);
+              for (int r = 0; r < 4; ++r) rb[s][r] = load4<VEC>(b_rsrc, voff, r * (int)P.ldb * 4);
             }
           }
         };
-        auto store = [&](const Regs& R, int bsel) {
+        auto store = [&](int bsel) {
           char* As = lds + bsel * (A_BYTES + B_BYTES);
           char* Bs = As + A_BYTES;
           // k beyond the piece is zeroed; rows beyond it are discarded later
 #pragma unroll
           for (int s = 0; s < A_PER; ++s) {
             const int row = a_row + s * (kThreads / 8);
-            f32x4 v = R.a[s];
+            f32x4 v = ra[s];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-              if (4 * a_kq + j >= R.klim) v[j] = 0.f;
+              if (4 * a_kq + j >= klim) v[j] = 0.f;
             if constexpr (F32) {
               *(f32x4*)(As + lds_off<true>(row, a_kq)) = v;
             } else {
@@ -186,107 +186,97 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
           for (int s = 0; s < B_PER; ++s) {
             const int u = t + s * kThreads;
             if (u < B_UNITS) {
-              const int nq = u % (BN / 4), kq = u / (BN / 4);
+              const int kq = u & 7, nq = u >> 3;
 #pragma unroll
               for (int c = 0; c < 4; ++c) {
                 float v[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = (4 * kq + r < R.klim) ? R.b[s][r][c] : 0.f;
+                for (int r = 0; r < 4; ++r) v[r] = (4 * kq + r < klim) ? rb[s][r][c] : 0.f;
                 const int n = 4 * nq + c;
                 if constexpr (F32) {
-                  *(f32x4*)(Bs + lds_off<true>(n, kq)) = (f32x4){v[0], v[1], v[2], v[3]};
+                  *(f32x4*)(Bs + lds_off<true, true>(n, kq)) = (f32x4){v[0], v[1], v[2], v[3]};
                 } else {
                   u32x2 parts[NS];
                   split4<NS>(v[0], v[1], v[2], v[3], parts);
 #pragma unroll
                   for (int p = 0; p < NS; ++p)
-                    *(u32x2*)(Bs + p * BN * ROWB + lds_off<false>(n, kq >> 1) + (kq & 1) * 8) = parts[p];
+                    *(u32x2*)(Bs + p * BN * ROWB + lds_off<false, true>(n, kq >> 1) + (kq & 1) * 8) = parts[p];
                 }
               }
             }
           }
         };
-        // One step: read all fragments of buffer bsel, then the matrix-core
-        // work, with the split of the next step (into the other buffer)
-        // available to the scheduler in between.
-        auto step = [&](int bsel, const Regs* next) {
+        auto step = [&](int bsel) {
           const char* As = lds + bsel * (A_BYTES + B_BYTES);
           const char* Bs = As + A_BYTES;
           if constexpr (F32) {
-            f32x4 fa[4][FM], fb[4][FN];
+            // lane half lh reads float chunk 2*s + lh (4 k values) of its row;
+            // instruction j of the chunk pairs component j of A and B
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
+              f32x4 fa[FM], fb[FN];
 #pragma unroll
-              for (int a = 0; a < FM; ++a) fa[s][a] = *(const f32x4*)(As + lds_off<true>(wr + a * 32 + l32, 2 * s + lh));
+              for (int a = 0; a < FM; ++a) fa[a] = *(const f32x4*)(As + lds_off<true>(wr + a * 32 + l32, 2 * s + lh));
 #pragma unroll
-              for (int b = 0; b < FN; ++b) fb[s][b] = *(const f32x4*)(Bs + lds_off<true>(wc + b * 32 + l32, 2 * s + lh));
-            }
-            if (next) store(*next, bsel ^ 1);
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
+              for (int b = 0; b < FN; ++b) fb[b] = *(const f32x4*)(Bs + lds_off<true, true>(wc + b * 32 + l32, 2 * s + lh));
 #pragma unroll
               for (int a = 0; a < FM; ++a)
 #pragma unroll
                 for (int b = 0; b < FN; ++b)
 #pragma unroll
-                  for (int j = 0; j < 4; ++j) acc[a][b] = mfma_f32(fa[s][a][j], fb[s][b][j], acc[a][b]);
+                  for (int j = 0; j < 4; ++j) acc[a][b] = mfma_f32(fa[a][j], fb[b][j], acc[a][b]);
+            }
           } else {
-            bf16x8 fa[2][FM][NS], fb[2][FN][NS];
+            // two k-halves of 16; lane half lh reads chunk 2*kh + lh; only one
+            // half's fragments are live at a time
 #pragma unroll
             for (int kh = 0; kh < 2; ++kh) {
+              bf16x8 fa[FM][NS], fb[FN][NS];
 #pragma unroll
               for (int a = 0; a < FM; ++a)
 #pragma unroll
                 for (int p = 0; p < NS; ++p)
-                  fa[kh][a][p] = *(const bf16x8*)(As + p * BM * ROWB + lds_off<false>(wr + a * 32 + l32, 2 * kh + lh));
+                  fa[a][p] = *(const bf16x8*)(As + p * BM * ROWB + lds_off<false>(wr + a * 32 + l32, 2 * kh + lh));
 #pragma unroll
               for (int b = 0; b < FN; ++b)
 #pragma unroll
                 for (int p = 0; p < NS; ++p)
-                  fb[kh][b][p] = *(const bf16x8*)(Bs + p * BN * ROWB + lds_off<false>(wc + b * 32 + l32, 2 * kh + lh));
-            }
-            if (next) store(*next, bsel ^ 1);
-#pragma unroll
-            for (int kh = 0; kh < 2; ++kh)
+                  fb[b][p] = *(const bf16x8*)(Bs + p * BN * ROWB + lds_off<false, true>(wc + b * 32 + l32, 2 * kh + lh));
 #pragma unroll
               for (int a = 0; a < FM; ++a)
 #pragma unroll
                 for (int b = 0; b < FN; ++b) {
                   f32x16 c = acc[a][b];
                   if constexpr (NS == 2) {
-                    c = mfma_bf16(fa[kh][a][1], fb[kh][b][0], c);
-                    c = mfma_bf16(fa[kh][a][0], fb[kh][b][1], c);
-                    c = mfma_bf16(fa[kh][a][0], fb[kh][b][0], c);
+                    c = mfma_bf16(fa[a][1], fb[b][0], c);
+                    c = mfma_bf16(fa[a][0], fb[b][1], c);
+                    c = mfma_bf16(fa[a][0], fb[b][0], c);
                   } else {
-                    c = mfma_bf16(fa[kh][a][2], fb[kh][b][0], c);
-                    c = mfma_bf16(fa[kh][a][0], fb[kh][b][2], c);
-                    c = mfma_bf16(fa[kh][a][1], fb[kh][b][1], c);
-                    c = mfma_bf16(fa[kh][a][1], fb[kh][b][0], c);
-                    c = mfma_bf16(fa[kh][a][0], fb[kh][b][1], c);
-                    c = mfma_bf16(fa[kh][a][0], fb[kh][b][0], c);
+                    c = mfma_bf16(fa[a][2], fb[b][0], c);
+                    c = mfma_bf16(fa[a][0], fb[b][2], c);
+                    c = mfma_bf16(fa[a][1], fb[b][1], c);
+                    c = mfma_bf16(fa[a][1], fb[b][0], c);
+                    c = mfma_bf16(fa[a][0], fb[b][1], c);
+                    c = mfma_bf16(fa[a][0], fb[b][0], c);
                   }
                   acc[a][b] = c;
                 }
+              if (kh == 0) __builtin_amdgcn_sched_barrier(0);
+            }
           }
         };
 
-        // prologue: step 0 into buffer 0, step 1 in flight
-        if (W.k0 < W.k1) {
-          load(R0, W.k0);
-          store(R0, 0);
+        // Double-buffered LDS with one barrier per step: step s is split into
+        // buffer s % 2 while the loads of step s+1 are issued before the
+        // matrix-core work of step s.
+        if (W.k0 < W.k1) load(W.k0);
+        int bsel = 0;
+        for (int kk = W.k0; kk < W.k1; kk += kBK) {
+          store(bsel);
           __syncthreads();
-          if (W.k0 + kBK < W.k1) load(R1, W.k0 + kBK);
-        }
-        // steps s (buffer s % 2); R1 holds step s+1 on even s, R0 on odd s
-        for (int kk = W.k0; kk < W.k1; kk += 2 * kBK) {
-          const bool has1 = kk + kBK < W.k1, has2 = kk + 2 * kBK < W.k1;
-          if (has2) load(R0, kk + 2 * kBK);
-          step(0, has1 ? &R1 : nullptr);
-          __syncthreads();
-          if (!has1) break;
-          if (kk + 3 * kBK < W.k1) load(R1, kk + 3 * kBK);
-          step(1, has2 ? &R0 : nullptr);
-          __syncthreads();
+          if (kk + kBK < W.k1) load(kk + kBK);
+          step(bsel);
+          bsel ^= 1;
         }
 
         // epilogue: lane holds column l32 of each 32x32 block, value 4g + r
@@ -349,6 +339,11 @@ hipError_t launch_prec(int tile, bool vec, const ProbRef& pr, const WorkItem* it
     case RING_T128x128: return launch_shape<PREC, 128, 128, 4, 2>(vec, pr, items, wg_off, nwg, xcd, ws, s);
     case RING_T128x64: return launch_shape<PREC, 128, 64, 4, 2>(vec, pr, items, wg_off, nwg, xcd, ws, s);
     case RING_T128x128W4: return launch_shape<PREC, 128, 128, 2, 2>(vec, pr, items, wg_off, nwg, xcd, ws, s);
+    case RING_T256x256:
+      // three bf16 parts of a 256 x 256 tile do not fit the 160 KiB of LDS
+      if constexpr (PREC != PREC_BF16X6)
+        return launch_shape<PREC, 256, 256, 2, 4>(vec, pr, items, wg_off, nwg, xcd, ws, s);
+      break;
   }
   return hipErrorInvalidValue;
 }
@@ -362,6 +357,7 @@ RingTileShape ring_tile_shape(int tile, int prec) {
     case RING_T128x128: return {128, 128, kBK};
     case RING_T128x64: return {128, 64, kBK};
     case RING_T128x128W4: return {128, 128, kBK};
+    case RING_T256x256: return {256, 256, kBK};
   }
   return {0, 0, 0};
 }

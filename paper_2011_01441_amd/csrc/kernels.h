@@ -28,9 +28,11 @@ hipError_t launch_semiring_bool(int tile, const ProbRef& pr, const WorkItem* ite
                                 hipStream_t s);
 
 // (+,x) ring kernel on matrix cores.
-// Tile shapes of the ring kernel (32 k per step): 8 waves (4 x 2) unless
-// marked W4 (4 waves, 2 x 2).
-enum RingTile : int { RING_T256x128 = 0, RING_T128x128 = 1, RING_T128x64 = 2, RING_T128x128W4 = 3 };
+// Tile shapes of the ring kernel (32 k per step): 8 waves (4 x 2, or 2 x 4
+// for 256 x 256) unless marked W4 (4 waves, 2 x 2).
+enum RingTile : int {
+  RING_T256x128 = 0, RING_T128x128 = 1, RING_T128x64 = 2, RING_T128x128W4 = 3, RING_T256x256 = 4
+};
 struct RingTileShape { int tm, tn, bk; };
 RingTileShape ring_tile_shape(int tile, int prec);
 hipError_t launch_ring(int prec, int tile, const ProbRef& pr, const WorkItem* items,

@@ -124,9 +124,10 @@ int choose_bool_tile(const std::vector<Piece>& pcs) {
 }
 
 int choose_ring_tile(const std::vector<Piece>& pcs, int prec) {
-  const int cand[3] = {RING_T256x128, RING_T128x128, RING_T128x64};
-  const double eff[3] = {1.0, 1.12, 1.5};
-  return choose_tile(pcs, cand, eff, 3, [prec](int t, int& tm, int& tn) {
+  const int cand[4] = {RING_T256x256, RING_T256x128, RING_T128x128, RING_T128x64};
+  const double eff[4] = {1.0, 1.1, 1.25, 1.6};
+  const int nc = prec == PREC_BF16X6 ? 3 : 4;
+  return choose_tile(pcs, cand + (4 - nc), eff + (4 - nc), nc, [prec](int t, int& tm, int& tn) {
     RingTileShape s = ring_tile_shape(t, prec);
     tm = s.tm;
     tn = s.tn;
