@@ -11,7 +11,8 @@ import os
 
 import torch
 
-__all__ = ["Context", "PacoError", "semiring_mm", "strassen_mm", "partition", "plan_export", "lib",
+__all__ = ["Context", "Server", "PacoError", "semiring_mm", "strassen_mm", "partition", "plan_export",
+           "batch_partition", "server_clock", "lib",
            "SEMIRING", "PRECISION", "INF", "NEG_INF", "library_path"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -75,6 +76,36 @@ class PartOpts(ctypes.Structure):
                 ("multi_piece", ctypes.c_int32)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("sr", ctypes.c_int),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64),
+                ("precision", ctypes.c_int), ("arrival_s", ctypes.c_double)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("precision", ctypes.c_int),
+                ("arrival_s", ctypes.c_double), ("launch_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("batch_id", ctypes.c_int32),
+                ("batch_size", ctypes.c_int32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_int32),
+                ("per_request", ctypes.c_int32), ("p", ctypes.c_int32),
+                ("batch_window_s", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("mean_batch", ctypes.c_double), ("p50_s", ctypes.c_double),
+                ("p99_s", ctypes.c_double), ("max_s", ctypes.c_double),
+                ("span_s", ctypes.c_double), ("ops", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -106,9 +137,21 @@ def lib():
                                  i64, ctypes.POINTER(i64)]
     L.paco_plan_export.argtypes = [i64, i64, i64, ci, ci, ctypes.c_int32, ctypes.c_int32, ci,
                                    ctypes.c_int32, ctypes.POINTER(PlanInfo), vp, vp, vp, vp]
+    L.paco_server_clock.restype = ctypes.c_double
+    L.paco_server_create.argtypes = [vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    L.paco_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.paco_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ci), ctypes.POINTER(RequestResult)]
+    L.paco_server_drain.argtypes = [vp]
+    L.paco_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.paco_server_destroy.argtypes = [vp]
+    L.paco_batch_partition.argtypes = [ctypes.POINTER(Request), ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(Piece), ctypes.POINTER(ctypes.c_int32), i64,
+                                       ctypes.POINTER(i64)]
     L.paco_timing_enable.argtypes = [vp, ci]
     L.paco_timing_read.argtypes = [vp, ctypes.POINTER(Timing)]
-    for name in ("paco_plan_export", "paco_timing_enable", "paco_timing_read", "paco_create", "paco_destroy", "paco_set_stream", "paco_semiring_mm",
+    for name in ("paco_server_create", "paco_server_submit", "paco_server_poll",
+                 "paco_server_drain", "paco_server_stats_get", "paco_server_destroy",
+                 "paco_batch_partition", "paco_plan_export", "paco_timing_enable", "paco_timing_read", "paco_create", "paco_destroy", "paco_set_stream", "paco_semiring_mm",
                  "paco_semiring_mm_ex", "paco_strassen_mm", "paco_verify_rows_f64",
                  "paco_partition"):
         getattr(L, name).restype = ci
@@ -285,3 +328,88 @@ def semiring_mm(A, B, semiring="ring", **kw):
 
 def strassen_mm(A, B, levels=2, leaf="bf16x3"):
     return _ctx().strassen_mm(A, B, levels, leaf)
+
+
+# ------------------------------------------------------------------ server
+
+def server_clock():
+    """The monotonic clock (seconds) the server stamps request times with."""
+    return lib().paco_server_clock()
+
+
+def _request(n, m, k, semiring, A=0, lda=0, B=0, ldb=0, C=0, ldc=0, precision="auto", arrival=0.0):
+    return Request(n, m, k, SEMIRING[semiring], A, lda, B, ldb, C, ldc, PRECISION[precision], arrival)
+
+
+def batch_partition(reqs, p):
+    """Host-only: pieces the server launches for a batch.  reqs: dicts with
+    n, m, k, semiring (and optional precision).  Returns piece dicts with the
+    request index under 'req'."""
+    L = lib()
+    arr = (Request * max(len(reqs), 1))(*[_request(r["n"], r["m"], r["k"], r["semiring"],
+                                                   precision=r.get("precision", "auto"))
+                                          for r in reqs])
+    cnt = ctypes.c_int64(0)
+    _check(L.paco_batch_partition(arr, len(reqs), p, None, None, 0, ctypes.byref(cnt)))
+    buf = (Piece * max(cnt.value, 1))()
+    rq = (ctypes.c_int32 * max(cnt.value, 1))()
+    _check(L.paco_batch_partition(arr, len(reqs), p, buf, rq, cnt.value, ctypes.byref(cnt)))
+    names = [f[0] for f in Piece._fields_]
+    out = []
+    for i in range(cnt.value):
+        d = {f: getattr(buf[i], f) for f in names}
+        d["req"] = rq[i]
+        out.append(d)
+    return out
+
+
+class Server:
+    """Batching request server on a device (see include/paco_server.h)."""
+
+    def __init__(self, ctx, hbm_budget=0, max_batch=0, per_request=False, p=0, window_s=0.0):
+        self._L = lib()
+        o = ServerOpts(hbm_budget, max_batch, 1 if per_request else 0, p, window_s)
+        h = ctypes.c_void_p()
+        _check(self._L.paco_server_create(ctx._h, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, A, B, C, semiring="ring", *, n=None, m=None, k=None, precision="auto",
+               arrival=0.0):
+        """Queue C = A (x) B.  Tensors may be row-strided views; boolean
+        operands need explicit n, m, k (bits).  Returns a ticket."""
+        sr = SEMIRING[semiring]
+        if sr != 3:
+            n, k = A.shape
+            m = B.shape[1]
+        r = Request(n, m, k, sr, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C), C.stride(0),
+                    PRECISION[precision], arrival)
+        t = ctypes.c_uint64(0)
+        _check(self._L.paco_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket):
+        done = ctypes.c_int(0)
+        r = RequestResult()
+        _check(self._L.paco_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(r)))
+        d = {f[0]: getattr(r, f[0]) for f in RequestResult._fields_}
+        d["precision"] = PRECISION_NAME.get(d["precision"], d["precision"])
+        return bool(done.value), d
+
+    def drain(self):
+        _check(self._L.paco_server_drain(self._h))
+
+    def stats(self):
+        st = ServerStats()
+        _check(self._L.paco_server_stats_get(self._h, ctypes.byref(st)))
+        return {f[0]: getattr(st, f[0]) for f in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.paco_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

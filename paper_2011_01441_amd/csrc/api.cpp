@@ -257,15 +257,7 @@ extern "C" paco_status paco_partition(int64_t n, int64_t m, int64_t k, const pac
 
 // -------------------------------------------------------------- semiring MM
 
-namespace {
-
-struct Norm {  // normalised call
-  paco_semiring sr;
-  int64_t n, m, k;           // logical sizes
-  int64_t mu, ku;            // kernel units of m and k-words (bool: words)
-  int64_t lda, ldb, ldc;     // kernel units
-  int prec;
-};
+namespace paco {
 
 int64_t words(int64_t bits) { return (bits + 31) / 32; }
 
@@ -276,6 +268,23 @@ int auto_precision(int64_t k) {
   // predicted value is at most 2^-21, i.e. k >= 4096.
   return k >= 4096 ? PREC_BF16X3 : PREC_BF16X6;
 }
+
+bool ring_vec_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t m, int64_t k) {
+  return (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0 && lda % 4 == 0 && ldb % 4 == 0 && k % 4 == 0 &&
+         m % 4 == 0;
+}
+
+}  // namespace paco
+
+namespace {
+
+struct Norm {  // normalised call
+  paco_semiring sr;
+  int64_t n, m, k;           // logical sizes
+  int64_t mu, ku;            // kernel units of m and k-words (bool: words)
+  int64_t lda, ldb, ldc;     // kernel units
+  int prec;
+};
 
 }  // namespace
 
@@ -498,6 +507,7 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   pr.base.lda = z.lda; pr.base.ldb = z.ldb; pr.base.ldc = z.ldc;
   pr.base.n = (int32_t)z.n; pr.base.m = (int32_t)z.m; pr.base.k = (int32_t)z.k;
   pr.base.accumulate = d->accumulate ? 1 : 0;
+  pr.vec_ok = ring_vec_ok(d->A, z.lda, d->B, z.ldb, z.m, z.k) ? 1 : 0;
   {
   TimeScope ts(ctx, 0);
   if (dp->fam == 0)

@@ -65,6 +65,11 @@ paco_status verify_sampled(paco_ctx ctx, int64_t n, int64_t m, int64_t k, const 
                            const float* B, int64_t ldb, const float* C, int64_t ldc, int rows,
                            uint64_t seed, paco_mm_result* res);
 void destroy_ctx_extras(paco_ctx ctx);
+int64_t words(int64_t bits);
+int auto_precision(int64_t k);
+bool ring_vec_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t m, int64_t k);
+void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
+                  int num_cus, DevPlan* np);
 
 // Brackets one kernel launch with timing events when timing is enabled.
 struct TimeScope {

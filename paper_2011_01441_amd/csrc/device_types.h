@@ -36,6 +36,10 @@ struct ProbRef {
   const Problem* table;
   Problem base;
   int64_t sA, sB, sC;  // element strides between consecutive problems
+  int32_t vec_ok;      // set by the host: every problem's A and B rows are
+                       // 16-byte aligned with lengths multiple of 4 (the
+                       // ring kernel may use 128-bit loads)
+  int32_t pad;
 };
 
 // A sub-cuboid [n0,n1) x [m0,m1) x [k0,k1) of problem `prob`.  out_off < 0:

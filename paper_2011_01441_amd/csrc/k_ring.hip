@@ -366,12 +366,9 @@ hipError_t launch_ring(int prec, int tile, const ProbRef& pr, const WorkItem* it
                        int nwg, int xcd, void* ws, hipStream_t s) {
   if (nwg <= 0) return hipSuccess;
   // 128-bit loads need 16-byte aligned rows and row lengths that are
-  // multiples of 4 (so no vector straddles the end of a matrix); batched
-  // problems use the base problem's layout.
-  const Problem& b = pr.base;
-  bool vec = pr.table == nullptr && ((uintptr_t)b.A % 16 == 0) && ((uintptr_t)b.B % 16 == 0) &&
-             b.lda % 4 == 0 && b.ldb % 4 == 0 && b.k % 4 == 0 && b.m % 4 == 0 && pr.sA % 4 == 0 &&
-             pr.sB % 4 == 0;
+  // multiples of 4 (so no vector straddles the end of a matrix); the host
+  // checks every problem of the launch and sets vec_ok.
+  const bool vec = pr.vec_ok != 0;
   switch (prec) {
     case PREC_FP32: return launch_prec<PREC_FP32>(tile, vec, pr, items, wg_off, nwg, xcd, ws, s);
     case PREC_BF16X3: return launch_prec<PREC_BF16X3>(tile, vec, pr, items, wg_off, nwg, xcd, ws, s);

@@ -144,6 +144,7 @@ extern "C" paco_status paco_strassen_mm(paco_ctx ctx, int64_t n, const float* A,
   pr.base.lda = pr.base.ldb = pr.base.ldc = h;
   pr.base.n = pr.base.m = pr.base.k = (int32_t)h;
   pr.sA = pr.sB = pr.sC = (int64_t)blk;
+  pr.vec_ok = (h % 4 == 0) ? 1 : 0;   // S, T blocks start 16-byte aligned when h % 4 == 0
   {
     TimeScope ts(ctx, 0);
     e = launch_ring(prec, dp->tile, pr, dp->d_items, dp->d_wg_off, dp->h.nwg, dp->h.xcd_remap, ctx->ws,

@@ -1,0 +1,90 @@
+"""GPU: the batching request server against the CPU oracle.
+
+Requests are views into resident operand pools (as a serving system keeps
+operands in HBM); every result is compared with the oracle: (min,+)
+bit-exact, ring within the componentwise bound."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_2011_01441_amd")
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def pools():
+    ra, rb = workloads.ring_operands(700, 700, 700, seed=5)
+    ma, mb = workloads.minplus_operands(700, 700, 700, seed=6)
+    return dict(ring=(ra, rb, torch.from_numpy(ra).to(DEV), torch.from_numpy(rb).to(DEV)),
+                minplus=(ma, mb, torch.from_numpy(ma).to(DEV), torch.from_numpy(mb).to(DEV)))
+
+
+def _run(srv, pools, shapes):
+    out = []
+    for i, (kind, n, m, k) in enumerate(shapes):
+        a, b, ad, bd = pools[kind]
+        C = torch.empty((n, m), dtype=ad.dtype, device=DEV)
+        t = srv.submit(ad[:n, :k], bd[:k, :m], C, kind)
+        out.append((t, kind, n, m, k, C))
+    srv.drain()
+    return out
+
+
+def _check(pools, srv, runs):
+    torch.cuda.synchronize()
+    for t, kind, n, m, k, C in runs:
+        done, res = srv.poll(t)
+        assert done and res["status"] == 0, res
+        a, b = pools[kind][0][:n, :k], pools[kind][1][:k, :m]
+        got = C.cpu().numpy()
+        if kind == "minplus":
+            assert np.array_equal(got, oracle.minplus(a, b)), (n, m, k)
+        else:
+            C64, S = oracle.ring_f64(a, b, with_abs=True)
+            err = np.max(np.abs(got - C64) / S)
+            assert err <= 2.0 ** -20, (n, m, k, res["precision"], np.log2(err))
+
+
+SHAPES = [("ring", 33, 47, 65), ("minplus", 100, 300, 50), ("ring", 640, 512, 700),
+          ("minplus", 1, 1, 1), ("ring", 129, 3, 333), ("minplus", 512, 640, 256),
+          ("ring", 64, 64, 64), ("minplus", 77, 91, 700)] * 3
+
+
+@pytest.mark.parametrize("per_request", [False, True])
+def test_server_mixed_batch_matches_oracle(ctx, pools, per_request):
+    print(f"case: server per_request={per_request}", flush=True)
+    srv = P.Server(ctx, per_request=per_request)
+    runs = _run(srv, pools, SHAPES)
+    _check(pools, srv, runs)
+    st = srv.stats()
+    assert st["completed"] == len(SHAPES) and st["failed"] == 0
+    if per_request:
+        assert st["batches"] == len(SHAPES)
+    srv.close()
+
+
+def test_server_small_budget_queues_and_rejects(ctx, pools):
+    print("case: server admission budget", flush=True)
+    budget = 3 * 4 * 640 * 700    # about one large request at a time
+    srv = P.Server(ctx, hbm_budget=budget)
+    runs = _run(srv, pools, SHAPES[:8])
+    _check(pools, srv, runs)
+    a, b, ad, bd = pools["ring"]
+    C = torch.empty((700, 700), device=DEV)
+    with pytest.raises(P.PacoError) as ei:
+        srv.submit(ad, bd, C, "ring")
+    assert ei.value.status == 4     # PACO_ERR_BUDGET
+    srv.close()
