@@ -147,6 +147,83 @@ def cpu_baseline(w, A, B, target_s):
                       f"{dt:.1f} s", "seconds": dt}
 
 
+def bench_server(torch, P, count, rate, check=32):
+    """Open-loop and saturation runs of the request server, batched vs
+    per-request launches, on views of resident operand pools."""
+    import oracle
+    import workloads as W
+    dev = torch.device("cuda:0")
+    reqs = W.server_stream(count=count, rate=rate, seed=0)
+    dmax = max(max(r["n"], r["m"], r["k"]) for r in reqs)
+    t0 = time.time()
+    ra, rb = W.ring_operands(dmax, dmax, dmax, seed=1)
+    ma, mb = W.minplus_operands(dmax, dmax, dmax, seed=1)
+    pools = {"ring": (ra, rb, torch.from_numpy(ra).to(dev), torch.from_numpy(rb).to(dev)),
+             "minplus": (ma, mb, torch.from_numpy(ma).to(dev), torch.from_numpy(mb).to(dev))}
+    log(f"server pools ({dmax}^2) in {time.time() - t0:.1f}s")
+    tot = {"ring": 0, "minplus": 0}
+    offs = []
+    for r in reqs:
+        offs.append(tot[r["kind"]])
+        tot[r["kind"]] += r["n"] * r["m"]
+    cbuf = {kd: torch.empty(max(v, 1), dtype=pools[kd][2].dtype, device=dev) for kd, v in tot.items()}
+    views = []
+    for r, o in zip(reqs, offs):
+        a, b = pools[r["kind"]][2], pools[r["kind"]][3]
+        C = cbuf[r["kind"]][o:o + r["n"] * r["m"]].view(r["n"], r["m"])
+        views.append((a[:r["n"], :r["k"]], b[:r["k"], :r["m"]], C))
+    ops = sum(2.0 * r["n"] * r["m"] * r["k"] for r in reqs)
+    out = {"requests": count, "rate_req_s": rate, "gop_total": ops / 1e9}
+    ctx = P.Context(0)
+    for per_req in (False, True):
+        mode = "per_request" if per_req else "batched"
+        for load in ("open_loop", "saturation"):
+            srv = P.Server(ctx, per_request=per_req, hbm_budget=64 << 30)
+            # warm the kernels once
+            for i in range(3):
+                A_, B_, C_ = views[i]
+                srv.submit(A_, B_, C_, reqs[i]["kind"])
+            srv.drain()
+            srv.close()
+            srv = P.Server(ctx, per_request=per_req, hbm_budget=64 << 30)
+            base = P.server_clock() + 0.02
+            tickets = []
+            for r, (A_, B_, C_) in zip(reqs, views):
+                arr = base + (r["t"] if load == "open_loop" else 0.0)
+                if load == "open_loop":
+                    while P.server_clock() < arr:
+                        pass
+                tickets.append(srv.submit(A_, B_, C_, r["kind"], arrival=arr))
+            srv.drain()
+            st = srv.stats()
+            srv.close()
+            out[f"{mode}_{load}"] = {
+                "p50_ms": round(st["p50_s"] * 1e3, 4), "p99_ms": round(st["p99_s"] * 1e3, 4),
+                "max_ms": round(st["max_s"] * 1e3, 4), "req_per_s": round(st["completed"] / st["span_s"], 1),
+                "gop_per_s": round(st["ops"] / st["span_s"] / 1e9, 1), "batches": st["batches"],
+                "mean_batch": round(st["mean_batch"], 2), "failed": st["failed"]}
+            log(f"server {mode} {load}: {out[f'{mode}_{load}']}")
+    # sampled correctness of the last run's results against the oracle
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    bad = 0
+    for i in rng.choice(count, size=min(check, count), replace=False):
+        r = reqs[i]
+        a, b = pools[r["kind"]][0][:r["n"], :r["k"]], pools[r["kind"]][1][:r["k"], :r["m"]]
+        rows = np.unique(rng.integers(0, r["n"], size=4))
+        got = views[i][2][torch.from_numpy(rows).to(dev)].cpu().numpy()
+        if r["kind"] == "minplus":
+            bad += int(not np.array_equal(got, oracle.minplus(a[rows], b)))
+        else:
+            C64, S = oracle.ring_f64(a, b, rows=rows, with_abs=True)
+            worst = max(worst, float(np.max(np.abs(got - C64) / S)))
+    out["check"] = {"sampled_requests": int(min(check, count)), "minplus_mismatches": bad,
+                    "ring_max_rel": worst}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +234,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--verify-rows", type=int, default=64)
+    ap.add_argument("--no-server", action="store_true", help="skip the request-server runs")
+    ap.add_argument("--server-requests", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -202,7 +281,7 @@ def main():
     grid = None
     if not args.no_grid and w["kind"] != "strassen":
         best = None
-        for sk in (1, 2, 4, 8, 16, 32, 64):
+        for sk in (1, 2, 4, 8, 16, 32, 64, 128):
             f = (lambda sk=sk: call(ctx, w, Ad, Bd, C, part="grid", split_k=sk))
             f()
             t = timed(torch, f, 3) * 1e3
@@ -226,6 +305,10 @@ def main():
         mrel, mabs, sd, sr = ctx.verify_rows(Ad, Bd, C, rows)
         err = {"normwise_sampled": math.sqrt(sd / sr) if sr > 0 else None,
                "max_rel_componentwise_sampled": mrel, "rows": int(rows.numel()), "bound": 2.0 ** -16}
+
+    server = None
+    if not args.no_server:
+        server = bench_server(torch, P, args.server_requests, 2000.0)
 
     cpu = None
     if not args.no_cpu:
@@ -258,6 +341,7 @@ def main():
         "grid_baseline": grid,
         "paco_vs_grid": round(grid["ms_per_step"] / ms, 4) if grid else None,
         "error": err,
+        "server": server,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

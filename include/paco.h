@@ -135,6 +135,11 @@ typedef struct paco_mm_desc {
                                    rows on the GPU (ring only); the call
                                    then synchronises the stream */
   uint64_t verify_seed;
+  double kcut_cost;             /* PACO mode: when the longest dimension of
+                                   the virtual cuboid is chosen, k counts as
+                                   k / kcut_cost (1 = the paper's rule; a
+                                   k-cut costs a temporary face written and
+                                   read back); 0 = library default */
 } paco_mm_desc;
 
 typedef struct paco_mm_result {
@@ -210,6 +215,7 @@ typedef struct paco_part_opts {
                                 cuts split in the ratio of the two halves'
                                 summed throughput (heterogeneous variant) */
   int32_t multi_piece;       /* 1: PACO MM pruned-BFS multi-piece mode */
+  double kcut_cost;          /* see paco_mm_desc (0 = 1, the paper's rule) */
 } paco_part_opts;
 
 /* Host-only.  Partition the n-by-m-by-k cuboid over opts->p processors.

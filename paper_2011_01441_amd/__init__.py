@@ -42,7 +42,7 @@ class MMDesc(ctypes.Structure):
                 ("accumulate", ctypes.c_int32), ("precision", ctypes.c_int),
                 ("part", ctypes.c_int), ("p", ctypes.c_int32),
                 ("grid_split_k", ctypes.c_int32), ("verify_rows", ctypes.c_int32),
-                ("verify_seed", ctypes.c_uint64)]
+                ("verify_seed", ctypes.c_uint64), ("kcut_cost", ctypes.c_double)]
 
 
 class MMResult(ctypes.Structure):
@@ -73,7 +73,7 @@ class PlanInfo(ctypes.Structure):
 class PartOpts(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("q_n", ctypes.c_int32), ("q_m", ctypes.c_int32),
                 ("q_k", ctypes.c_int32), ("weights", ctypes.POINTER(ctypes.c_double)),
-                ("multi_piece", ctypes.c_int32)]
+                ("multi_piece", ctypes.c_int32), ("kcut_cost", ctypes.c_double)]
 
 
 class Request(ctypes.Structure):
@@ -166,11 +166,11 @@ def _check(st, ctx=None):
         raise PacoError(st, f"{L.paco_status_string(st).decode()}: {msg}")
 
 
-def partition(n, m, k, p, q=(1, 1, 1), weights=None, multi_piece=False):
+def partition(n, m, k, p, q=(1, 1, 1), weights=None, multi_piece=False, kcut_cost=1.0):
     """Host-only PACO partition (MM-1-Piece, or pruned-BFS multi-piece):
     a list of dicts with n0,n1,m0,m1,k0,k1, proc, temp, round, depth."""
     L = lib()
-    o = PartOpts(p, q[0], q[1], q[2], None, 1 if multi_piece else 0)
+    o = PartOpts(p, q[0], q[1], q[2], None, 1 if multi_piece else 0, kcut_cost)
     if weights is not None:
         arr = (ctypes.c_double * p)(*[float(w) for w in weights])
         o.weights = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
@@ -244,7 +244,7 @@ class Context:
 
     def semiring_mm(self, A, B, semiring="ring", *, n=None, m=None, k=None, C=None,
                     accumulate=False, precision="auto", part="paco", p=0, split_k=0,
-                    verify_rows=0, verify_seed=0, return_result=False):
+                    verify_rows=0, verify_seed=0, kcut_cost=0.0, return_result=False):
         """C = A (x) B.  Boolean operands are bit-packed int32 words; pass
         their logical sizes n, m, k.  Returns C (and a result dict)."""
         sr = SEMIRING[semiring]
@@ -267,7 +267,7 @@ class Context:
             self._check_tensor(C, "C", dt)
         d = MMDesc(n, m, k, sr, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C), C.stride(0),
                    1 if accumulate else 0, PRECISION[precision], PART[part], p, split_k,
-                   verify_rows, verify_seed)
+                   verify_rows, verify_seed, kcut_cost)
         r = MMResult()
         self._stream()
         _check(self._L.paco_semiring_mm_ex(self._h, ctypes.byref(d), ctypes.byref(r)), self._h)

@@ -237,6 +237,8 @@ extern "C" paco_status paco_partition(int64_t n, int64_t m, int64_t k, const pac
   po.q[1] = o->q_m > 0 ? o->q_m : 1;
   po.q[2] = o->q_k > 0 ? o->q_k : 1;
   po.weights = o->weights;
+  po.kcut_cost = o->kcut_cost > 0 ? o->kcut_cost : 1.0;
+  if (!(po.kcut_cost >= 1.0) || !std::isfinite(po.kcut_cost)) return PACO_ERR_INVALID_ARG;
   if (o->weights)
     for (int i = 0; i < o->p; ++i)
       if (!(o->weights[i] > 0) || !std::isfinite(o->weights[i])) return PACO_ERR_INVALID_ARG;
@@ -258,6 +260,22 @@ extern "C" paco_status paco_partition(int64_t n, int64_t m, int64_t k, const pac
 // -------------------------------------------------------------- semiring MM
 
 namespace paco {
+
+// k-cut cost of the PACO partition when the caller gives none.  A k-cut
+// makes the upper cuboid write a temporary face that is read back by the
+// reduction; next to the matrix-core ring kernel that round trip costs about
+// as much as the piece's work on a face 16 times larger, while the VALU
+// semirings spend far longer per element and keep the paper's rule (1).
+// Measured on (2048, 1024, 65536) and 8192^3 (ring) and on the (min,+) and
+// boolean shapes; PACO_KCUT_COST in the environment overrides it.
+double default_kcut_cost(int sr) {
+  const char* e = getenv("PACO_KCUT_COST");
+  if (e) {
+    double v = atof(e);
+    return v >= 1.0 ? v : 1.0;
+  }
+  return sr == PACO_SR_PLUS_TIMES_F32 ? 16.0 : 1.0;
+}
 
 int64_t words(int64_t bits) { return (bits + 31) / 32; }
 
@@ -292,7 +310,7 @@ namespace paco {
 
 // Host part of a semiring MM plan: partition, tile choice, work lists.
 void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
-                  int num_cus, DevPlan* np) {
+                  int num_cus, DevPlan* np, double kcut_cost) {
   const bool is_bool = sr == PACO_SR_OR_AND_B1;
   const int64_t mu = is_bool ? words(m) : m, ku = is_bool ? words(k) : k;
   const int fam = sr == PACO_SR_PLUS_TIMES_F32 ? 2 : (is_bool ? 1 : 0);
@@ -301,6 +319,7 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
   if (part == PACO_PART_PACO) {
     PartOpts po;
     po.p = p;
+    po.kcut_cost = kcut_cost;
     if (fam == 1) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
     else if (fam == 2) { po.q[0] = 16; po.q[1] = 16; po.q[2] = 32; }
     pcs = partition_mm1(n, m, k, po);
@@ -312,7 +331,7 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
     if (fam == 2 && getenv("PACO_RING_TILE")) tile = atoi(getenv("PACO_RING_TILE"));
   } else {
     if (fam == 0) {
-      tile = m <= 64 ? INT_T256x64 : INT_T128x128;
+      tile = m <= 64 ? INT_T256x64 : (n <= 64 ? INT_T64x128 : INT_T128x128);
       IntTileShape ts = int_tile_shape(tile);
       tm = ts.tm; tn = ts.tn;
     } else if (fam == 1) {
@@ -320,7 +339,9 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
       BoolTileShape ts = bool_tile_shape(tile);
       tm = ts.tm; tn = ts.tnw * 32;
     } else {
-      tile = RING_T128x128;
+      // the largest tile the output fills (the same microkernels PACO uses)
+      tile = (n >= 256 && m >= 256 && prec != PREC_BF16X6) ? RING_T256x256
+             : (n >= 256 ? RING_T256x128 : (m >= 128 ? RING_T128x128 : RING_T128x64));
       if (getenv("PACO_RING_TILE")) tile = atoi(getenv("PACO_RING_TILE"));
       RingTileShape ts = ring_tile_shape(tile, prec);
       tm = ts.tm; tn = ts.tn; bk = ts.bk;
@@ -356,7 +377,7 @@ extern "C" paco_status paco_plan_export(int64_t n, int64_t m, int64_t k, paco_se
   int pr = -1;
   if (sr == PACO_SR_PLUS_TIMES_F32) pr = prec == PACO_PREC_AUTO ? auto_precision(k) : (int)prec;
   DevPlan dp;
-  make_mm_plan((int)sr, n, m, k, (int)part, p, split_k, pr, num_cus, &dp);
+  make_mm_plan((int)sr, n, m, k, (int)part, p, split_k, pr, num_cus, &dp, default_kcut_cost((int)sr));
   const HostPlan& h = dp.h;
   const bool fill = items && wg_off && tiles && srcs;
   if (fill) {
@@ -429,7 +450,8 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
     return PACO_ERR_INVALID_ARG;
   }
   if (d->precision < PACO_PREC_FP32 || d->precision > PACO_PREC_AUTO || d->part < PACO_PART_PACO ||
-      d->part > PACO_PART_GRID || d->p < 0 || d->grid_split_k < 0 || d->verify_rows < 0) {
+      d->part > PACO_PART_GRID || d->p < 0 || d->grid_split_k < 0 || d->verify_rows < 0 ||
+      !(d->kcut_cost == 0 || (d->kcut_cost >= 1 && std::isfinite(d->kcut_cost)))) {
     set_err(ctx, "invalid option");
     return PACO_ERR_INVALID_ARG;
   }
@@ -480,8 +502,9 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
 
   // ---- plan
   char key[256];
-  snprintf(key, sizeof key, "mm/%d/%lld/%lld/%lld/%d/%d/%d/%d", (int)d->sr, (long long)z.n,
-           (long long)z.m, (long long)z.k, (int)d->part, p, d->grid_split_k, z.prec);
+  const double kc = d->kcut_cost > 0 ? d->kcut_cost : default_kcut_cost((int)d->sr);
+  snprintf(key, sizeof key, "mm/%d/%lld/%lld/%lld/%d/%d/%d/%d/%g", (int)d->sr, (long long)z.n,
+           (long long)z.m, (long long)z.k, (int)d->part, p, d->grid_split_k, z.prec, kc);
   DevPlan* dp = nullptr;
   auto itp = ctx->plans.find(key);
   if (itp != ctx->plans.end()) {
@@ -489,7 +512,7 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   } else {
     std::unique_ptr<DevPlan> np(new DevPlan());
     make_mm_plan((int)d->sr, z.n, z.m, z.k, (int)d->part, p, d->grid_split_k, z.prec, ctx->num_cus,
-                 np.get());
+                 np.get(), kc);
     paco_status st = upload_plan(ctx, np.get());
     if (st != PACO_OK) return st;
     dp = np.get();

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "ctx.h"
 #include "device_types.h"
 
 namespace paco {
@@ -46,6 +47,7 @@ void split_rec(const std::vector<BatchReq>& reqs, const std::vector<int>& ids, s
       const BatchReq& r = reqs[ids[a]];
       PartOpts po;
       po.p = P;
+      po.kcut_cost = default_kcut_cost(r.sr);
       const int g = batch_group(r);
       if (g == G_BOOL) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
       else if (g <= G_RING_X6) { po.q[0] = 16; po.q[1] = 16; po.q[2] = 32; }

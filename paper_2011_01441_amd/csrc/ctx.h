@@ -69,7 +69,8 @@ int64_t words(int64_t bits);
 int auto_precision(int64_t k);
 bool ring_vec_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t m, int64_t k);
 void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
-                  int num_cus, DevPlan* np);
+                  int num_cus, DevPlan* np, double kcut_cost);
+double default_kcut_cost(int sr);
 
 // Brackets one kernel launch with timing events when timing is enabled.
 struct TimeScope {

@@ -30,8 +30,8 @@ struct ROr {
   static __device__ __forceinline__ T op(T a, T b) { return a | b; }
 };
 
-// One workgroup per tile; thread t owns VEC consecutive columns of each
-// row of the tile.  Sources are read in batches of 8 so their loads are in
+// One workgroup per tile; the tile's (row, VEC columns) units are spread
+// over the threads.  Sources are read in batches of 8 so their loads are in
 // flight together, and folded strictly in list (ascending-k) order.
 template <class T, int VEC>
 __device__ __forceinline__ void load_vec(const T* p, T x[VEC]) {
@@ -61,34 +61,37 @@ __global__ __launch_bounds__(256) void k_reduce(ProbRef pr, const RedTile* __res
   const int i0 = uni(tl.i0), i1 = uni(tl.i1), j1 = uni(tl.j1);
   const int s0 = uni(tl.s0), s1 = uni(tl.s1);
   T* C = (T*)P.C;
-  for (int j = uni(tl.j0) + (int)threadIdx.x * VEC; j < j1; j += 256 * VEC) {
-    for (int i = i0; i < i1; ++i) {
-      T* cp = C + (int64_t)i * P.ldc + j;
-      T v[VEC];
-      load_vec<T, VEC>(cp, v);
-      auto src_ptr = [&](int s) {
-        const RedSrc S = srcs[s];
-        return ws + S.off + (int64_t)(i - S.r0) * S.ld + (j - S.c0);
-      };
-      int s = s0;
-      for (; s + 8 <= s1; s += 8) {  // eight loads in flight, folded in order
-        T x[8][VEC];
+  // work unit = (row, VEC-column group) of the tile; 256 units in flight
+  const int j0 = uni(tl.j0);
+  const int wv = (j1 - j0 + VEC - 1) / VEC;
+  const int units = wv * (i1 - i0);
+  for (int u = (int)threadIdx.x; u < units; u += 256) {
+    const int i = i0 + u / wv, j = j0 + (u % wv) * VEC;
+    T* cp = C + (int64_t)i * P.ldc + j;
+    T v[VEC];
+    load_vec<T, VEC>(cp, v);
+    auto src_ptr = [&](int s) {
+      const RedSrc S = srcs[s];
+      return ws + S.off + (int64_t)(i - S.r0) * S.ld + (j - S.c0);
+    };
+    int s = s0;
+    for (; s + 8 <= s1; s += 8) {  // eight loads in flight, folded in order
+      T x[8][VEC];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) load_vec<T, VEC>(src_ptr(s + u), x[u]);
+      for (int q = 0; q < 8; ++q) load_vec<T, VEC>(src_ptr(s + q), x[q]);
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+      for (int q = 0; q < 8; ++q)
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) v[e] = R::op(v[e], x[u][e]);
-      }
-      for (; s < s1; ++s) {
-        T x[VEC];
-        load_vec<T, VEC>(src_ptr(s), x);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) v[e] = R::op(v[e], x[e]);
-      }
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) gstore(cp + e, v[e]);
+        for (int e = 0; e < VEC; ++e) v[e] = R::op(v[e], x[q][e]);
     }
+    for (; s < s1; ++s) {
+      T x[VEC];
+      load_vec<T, VEC>(src_ptr(s), x);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) v[e] = R::op(v[e], x[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) gstore(cp + e, v[e]);
   }
 }
 

@@ -16,7 +16,8 @@
 // Readings where the paper is silent: ties among equally long dimensions go
 // n, then m, then k (a k-cut costs a temporary face); cuts land on multiples
 // of a per-dimension quantum, rounded to nearest; a dimension shorter than
-// two quanta is not cut while another one can be.
+// two quanta is not cut while another one can be.  An optional k-cut cost
+// divides k's virtual length in that choice (1 keeps the paper's rule).
 #include "partition.h"
 
 #include <algorithm>
@@ -34,7 +35,8 @@ struct Box {
 
 // Longest virtual dimension (ties n, m, k) among those whose real length
 // still allows a cut on the quantum grid; if none does, the longest one.
-int pick_dim(const double v[3], const Box& b, const int64_t q[3]) {
+int pick_dim(const double v_in[3], const Box& b, const int64_t q[3], double kcost) {
+  const double v[3] = {v_in[0], v_in[1], v_in[2] / kcost};
   int best = -1;
   for (int d = 0; d < 3; ++d) {
     if (b.len(d) < 2 * q[d]) continue;
@@ -73,7 +75,7 @@ void mm1_rec(const Box& b, const double v[3], int p0, int p1, int depth, const P
     out.push_back(make_piece(b, p0, 0, depth));
     return;
   }
-  int d = pick_dim(v, b, o.q);
+  int d = pick_dim(v, b, o.q, o.kcut_cost);
   int pl = P / 2;
   double wl = wprefix[p0 + pl] - wprefix[p0];
   double wa = wprefix[p1] - wprefix[p0];
@@ -127,7 +129,7 @@ std::vector<Piece> partition_multi(int64_t n, int64_t m, int64_t k, const PartOp
     for (const Node& nd : level) {
       // even division of the longest side (the cuboid's own dimensions)
       double v[3] = {(double)nd.b.len(0), (double)nd.b.len(1), (double)nd.b.len(2)};
-      int d = pick_dim(v, nd.b, o.q);
+      int d = pick_dim(v, nd.b, o.q, o.kcut_cost);
       if (nd.b.len(d) < 2 * o.q[d]) {  // this one is a base case already
         next.push_back({nd.b, nd.depth});
         continue;

@@ -17,6 +17,10 @@ struct PartOpts {
   int64_t q[3] = {1, 1, 1};      // cut quanta for n, m, k
   const double* weights = nullptr;
   bool multi_piece = false;
+  // k counts as k / kcut_cost when the longest dimension is chosen (1 = the
+  // paper's rule; larger values prefer n and m cuts, which need no
+  // temporary face)
+  double kcut_cost = 1.0;
 };
 
 // MM-1-Piece (corollary mm-1-piece): exactly p pieces, piece j on proc j.

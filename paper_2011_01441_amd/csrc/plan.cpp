@@ -117,7 +117,7 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
         // 1024 elements (many workgroups: the fold is bandwidth-bound)
         int64_t i0 = rb[r], i1 = rb[r + 1], j0 = cb[c], j1 = cb[c + 1];
         int64_t cw = std::min<int64_t>(j1 - j0, 256 * vec);
-        int64_t rh = std::max<int64_t>(1, 1024 / cw);
+        int64_t rh = std::max<int64_t>(1, (256 * vec) / cw);
         for (int64_t ii = i0; ii < i1; ii += rh)
           for (int64_t jj = j0; jj < j1; jj += cw) {
             RedTile t;

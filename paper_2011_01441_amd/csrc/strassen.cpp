@@ -99,6 +99,7 @@ extern "C" paco_status paco_strassen_mm(paco_ctx ctx, int64_t n, const float* A,
     PartOpts po;
     po.p = p;
     po.q[0] = 16; po.q[1] = 16; po.q[2] = 32;
+    po.kcut_cost = default_kcut_cost(PACO_SR_PLUS_TIMES_F32);
     std::vector<Piece> pcs = partition_mm1((int64_t)nleaf * h, h, h, po);
     std::vector<TaggedPiece> tp;
     std::vector<Piece> local;

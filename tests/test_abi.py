@@ -1,0 +1,74 @@
+"""The C ABI: libpaco.so loads, exports every function declared in
+include/*.h, and its host-only calls validate their arguments."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+import torch
+
+P = pytest.importorskip("paper_2011_01441_amd")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for mt in re.finditer(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s+(paco_[a-z_0-9]+)\s*\(", src, re.M):
+            names.add(mt.group(1))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared()
+    assert {"paco_semiring_mm", "paco_strassen_mm", "paco_partition", "paco_server_submit"} <= names
+    L = ctypes.CDLL(P.library_path)
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    L = P.lib()
+    for s in range(8):
+        assert L.paco_status_string(s)
+    assert L.paco_status_string(0) == b"ok"
+
+
+def test_partition_argument_checks():
+    L = P.lib()
+    cnt = ctypes.c_int64()
+    o = P.PartOpts(0, 1, 1, 1, None, 0, 1.0)       # p = 0
+    assert L.paco_partition(4, 4, 4, ctypes.byref(o), None, 0, ctypes.byref(cnt)) == 1
+    o = P.PartOpts(4, 1, 1, 1, None, 0, 0.5)       # k-cut cost below 1
+    assert L.paco_partition(4, 4, 4, ctypes.byref(o), None, 0, ctypes.byref(cnt)) == 1
+    o = P.PartOpts(4, 1, 1, 1, None, 0, 1.0)
+    assert L.paco_partition(-1, 4, 4, ctypes.byref(o), None, 0, ctypes.byref(cnt)) == 1
+    w = (ctypes.c_double * 4)(1.0, 0.0, 1.0, 1.0)  # non-positive throughput
+    o = P.PartOpts(4, 1, 1, 1, ctypes.cast(w, ctypes.POINTER(ctypes.c_double)), 0, 1.0)
+    assert L.paco_partition(4, 4, 4, ctypes.byref(o), None, 0, ctypes.byref(cnt)) == 1
+
+
+def test_plan_export_argument_checks():
+    L = P.lib()
+    info = P.PlanInfo()
+    assert L.paco_plan_export(0, 4, 4, 0, 0, 256, 0, 3, 256, ctypes.byref(info), None, None, None, None) == 1
+    assert L.paco_plan_export(4, 4, 4, 9, 0, 256, 0, 3, 256, ctypes.byref(info), None, None, None, None) == 1
+    assert L.paco_plan_export(4, 4, 4, 1, 0, 256, 0, 3, 256, ctypes.byref(info), None, None, None, None) == 0
+
+
+def test_null_context_is_rejected():
+    L = P.lib()
+    assert L.paco_semiring_mm(None, 4, 4, 4, 1, None, None, None) == 1
+    assert L.paco_strassen_mm(None, 4, None, None, None, 1, 1) == 1
+    assert L.paco_destroy(None) == 1
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-device error path")
+def test_create_without_device_fails_cleanly():
+    L = P.lib()
+    h = ctypes.c_void_p()
+    assert L.paco_create(ctypes.byref(h), 0, 0) != 0
+    assert not h.value

@@ -54,7 +54,8 @@ def test_batch_pieces_do_not_overlap_within_a_request():
         assert (cube == 1).all()
 
 
-def test_single_large_request_gets_all_processors_like_mm1piece():
+def test_single_large_request_gets_all_processors_like_mm1piece(monkeypatch):
+    monkeypatch.setenv("PACO_KCUT_COST", "1")   # the paper's longest-dimension rule
     pieces = P.batch_partition([dict(n=2048, m=1024, k=65536, semiring="ring",
                                      precision="bf16x3")], 256)
     assert len(pieces) == 256 and len({pc["proc"] for pc in pieces}) == 256

@@ -89,12 +89,23 @@ def test_ring_plan_replay_small_integers(n, m, k, p):
     np.testing.assert_array_equal(C, oracle.ring_i64(A.astype(np.int64), B.astype(np.int64)))
 
 
-def test_plan_sizes_match_paper_shapes():
+def test_plan_sizes_match_paper_shapes(monkeypatch):
     # long k: (2048, 1024, 65536) on 256 processors -> 512 x 1024 x 1024 pieces,
-    # k cut 64-way: 252 temporary faces (4 n-blocks x 63)
+    # k cut 64-way: 252 temporary faces (4 n-blocks x 63) under the paper's
+    # longest-dimension rule (k-cut cost 1)
+    monkeypatch.setenv("PACO_KCUT_COST", "1")
     items, wg, tiles, srcs, info = P.plan_export(2048, 1024, 65536, "ring", p=256,
                                                  precision="bf16x3")
     ext = items[:, [2, 4, 6]] - items[:, [1, 3, 5]]
     assert (ext == [512, 1024, 1024]).all()
     assert (items[:, 7] >= 0).sum() == 252
     assert info["xcd_remap"] == 1 and info["n_wg"] == 256
+
+
+def test_ring_default_kcut_cost_prefers_n_and_m_cuts():
+    # the ring path's default k-cut cost (16): k is cut only while it is more
+    # than 16 times longer than n and m -> 256 x 256 x 8192 pieces on (2048,
+    # 1024, 65536)
+    items, *_ = P.plan_export(2048, 1024, 65536, "ring", p=256, precision="bf16x3")
+    ext = items[:, [2, 4, 6]] - items[:, [1, 3, 5]]
+    assert (ext == [256, 256, 8192]).all()
