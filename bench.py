@@ -51,6 +51,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant kernel from the committed PMC
+    summary, or None when there is none for this workload or the kernel
+    source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", " ", "`")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2011_01441_amd", "csrc", f"{kv.get('kernel', '')}.hip")
+    if not os.path.exists(src) or "traffic_bytes_per_launch" not in kv:
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if sha != kv.get("kernel_source_sha256_prefix"):
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def make_inputs(w, torch, dev):
     import workloads as W
     kind = w["kind"]
@@ -236,6 +258,8 @@ def main():
     ap.add_argument("--verify-rows", type=int, default=64)
     ap.add_argument("--no-server", action="store_true", help="skip the request-server runs")
     ap.add_argument("--server-requests", type=int, default=4096)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -256,6 +280,15 @@ def main():
         C = torch.empty((w["n"], w["n"]), dtype=torch.float32, device=dev)
     else:
         C = torch.empty((w["n"], w["m"]), dtype=Ad.dtype, device=dev)
+
+    if args.calib_copy:
+        # known traffic: a 1 GiB fill (writes 2^30 bytes) and a sum over it
+        # (reads 2^30 bytes)
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        tot = src.sum()
+        torch.cuda.synchronize()
+        log(f"calibration sum {float(tot):.0f}")
+        del src
 
     # ---- PACO path
     res = None
@@ -303,7 +336,14 @@ def main():
         call(ctx, w, Ad, Bd, C)
         rows = torch.arange(0, w["n"], max(1, w["n"] // 64), device=dev)
         mrel, mabs, sd, sr = ctx.verify_rows(Ad, Bd, C, rows)
-        err = {"normwise_sampled": math.sqrt(sd / sr) if sr > 0 else None,
+        # normwise: ||C - C64||_F / (||A||_F ||B||_F), the numerator
+        # extrapolated from the sampled rows
+        na = float(np.linalg.norm(A.astype(np.float64)))
+        nb = float(np.linalg.norm(B.astype(np.float64)))
+        diff_f = math.sqrt(sd * w["n"] / rows.numel())
+        nw = diff_f / (na * nb)
+        err = {"normwise": nw, "log2": math.log2(nw) if nw > 0 else None,
+               "relative_to_C64": math.sqrt(sd / sr) if sr > 0 else None,
                "max_rel_componentwise_sampled": mrel, "rows": int(rows.numel()), "bound": 2.0 ** -16}
 
     server = None
@@ -335,7 +375,7 @@ def main():
                    "kcut_faces": res["n_kcuts"] if res else None,
                    "parallelism": "one GPU, 256 CUs"},
         "roofline": {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.workload),
                      "kernel_ms": round(kern_ms, 4), "reduce_ms": round(red_ms, 4),
                      "other_ms": round(other_ms, 4), "work_per_launch": work},
         "grid_baseline": grid,
