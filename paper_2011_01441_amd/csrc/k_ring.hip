@@ -113,6 +113,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
   constexpr int B_PER = (B_UNITS + kThreads - 1) / kThreads;
   static_assert(A_UNITS % kThreads == 0, "A load split");
   static_assert(B_UNITS % kThreads == 0 || B_UNITS < kThreads, "B load split");
+  constexpr int NLD = A_PER + 4 * B_PER;         // 128-bit loads per thread and step
+  constexpr int NB = FM * FN;                    // 32x32 blocks per wave
   __shared__ __align__(16) char lds[2 * (A_BYTES + B_BYTES)];
 
   const int t = threadIdx.x;
@@ -144,34 +146,59 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
         const int a_soff = (kThreads / 8) * (int)P.lda * 4;
         // B unit u = t + s*kThreads: k-quad u % 8, n-quad u / 8
         f32x4 ra[A_PER], rb[B_PER][4];
-        int klim = 0;
-        auto load = [&](int kk) {
+        int klim = 0, lkk = 0;
+        // A step at or past the end of the k-range reads through empty
+        // buffer resources (every lane gets 0, no memory is touched), so the
+        // pipeline below can fetch one step ahead without a branch.
+        const auto a_none = make_rsrc(A, 0, 0, 0);
+        __amdgpu_buffer_rsrc_t la = a_none, lb = a_none;
+        // prep(kk) sets up the fetch of step kk; load_unit(i) issues its
+        // i-th 128-bit load per thread (A units first, then the four rows of
+        // each B unit)
+        auto prep = [&](int kk) {
           klim = W.k1 - kk;
-#pragma unroll
-          for (int s = 0; s < A_PER; ++s) ra[s] = load4<VEC>(a_rsrc, a_voff0 + kk * 4, s * a_soff);
-          const auto b_rsrc = make_rsrc(B + (int64_t)kk * P.ldb, P.k - kk, P.ldb, P.m);
-#pragma unroll
-          for (int s = 0; s < B_PER; ++s) {
+          lkk = kk;
+          const bool live = kk < W.k1;
+          la = live ? a_rsrc : a_none;
+          lb = make_rsrc(B + (int64_t)kk * P.ldb, live ? P.k - kk : 0, P.ldb, P.m);
+        };
+        auto load_unit = [&](int i) {
+          if (i < A_PER) {
+            ra[i] = load4<VEC>(la, a_voff0 + lkk * 4, i * a_soff);
+          } else {
+            const int s = (i - A_PER) / 4, r = (i - A_PER) % 4;
             const int u = t + s * kThreads;
-            if (u < B_UNITS) {
+            if (B_UNITS % kThreads == 0 || u < B_UNITS) {
               const int kq = u & 7, nq = u >> 3;
               const int voff = ((4 * kq) * (int)P.ldb + j0 + 4 * nq) * 4;
-#pragma unroll
-              for (int r = 0; r < 4; ++r) rb[s][r] = load4<VEC>(b_rsrc, voff, r * (int)P.ldb * 4);
+              rb[s][r] = load4<VEC>(lb, voff, r * (int)P.ldb * 4);
             }
           }
         };
-        auto store = [&](int bsel) {
-          char* As = lds + bsel * (A_BYTES + B_BYTES);
-          char* Bs = As + A_BYTES;
-          // k beyond the piece is zeroed; rows beyond it are discarded later
+        // k beyond the piece is zeroed in the registers before the step is
+        // stored (a uniform branch, taken on a piece's last step only); rows
+        // and columns beyond it are discarded by the epilogue.
+        auto mask_regs = [&] {
 #pragma unroll
-          for (int s = 0; s < A_PER; ++s) {
-            const int row = a_row + s * (kThreads / 8);
-            f32x4 v = ra[s];
+          for (int i = 0; i < A_PER; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-              if (4 * a_kq + j >= klim) v[j] = 0.f;
+              if (4 * a_kq + j >= klim) ra[i][j] = 0.f;
+#pragma unroll
+          for (int s = 0; s < B_PER; ++s)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (4 * ((t + s * kThreads) & 7) + r >= klim) rb[s][r] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        };
+        // store_unit(bsel, i): split and write the data of load unit i (for
+        // B: column i % 4 of unit (i - A_PER) / 4, which needs all four of
+        // its row loads) into LDS buffer bsel.
+        auto store_unit = [&](int bsel, int i) {
+          char* As = lds + bsel * (A_BYTES + B_BYTES);
+          char* Bs = As + A_BYTES;
+          if (i < A_PER) {
+            const int row = a_row + i * (kThreads / 8);
+            f32x4 v = ra[i];
             if constexpr (F32) {
               *(f32x4*)(As + lds_off<true>(row, a_kq)) = v;
             } else {
@@ -181,32 +208,45 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
               for (int p = 0; p < NS; ++p)
                 *(u32x2*)(As + p * BM * ROWB + lds_off<false>(row, a_kq >> 1) + (a_kq & 1) * 8) = parts[p];
             }
-          }
-#pragma unroll
-          for (int s = 0; s < B_PER; ++s) {
+          } else {
+            const int s = (i - A_PER) / 4, c = (i - A_PER) % 4;
             const int u = t + s * kThreads;
-            if (u < B_UNITS) {
+            if (B_UNITS % kThreads == 0 || u < B_UNITS) {
               const int kq = u & 7, nq = u >> 3;
+              float v[4];
 #pragma unroll
-              for (int c = 0; c < 4; ++c) {
-                float v[4];
+              for (int r = 0; r < 4; ++r) v[r] = rb[s][r][c];
+              const int n = 4 * nq + c;
+              if constexpr (F32) {
+                *(f32x4*)(Bs + lds_off<true, true>(n, kq)) = (f32x4){v[0], v[1], v[2], v[3]};
+              } else {
+                u32x2 parts[NS];
+                split4<NS>(v[0], v[1], v[2], v[3], parts);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = (4 * kq + r < klim) ? rb[s][r][c] : 0.f;
-                const int n = 4 * nq + c;
-                if constexpr (F32) {
-                  *(f32x4*)(Bs + lds_off<true, true>(n, kq)) = (f32x4){v[0], v[1], v[2], v[3]};
-                } else {
-                  u32x2 parts[NS];
-                  split4<NS>(v[0], v[1], v[2], v[3], parts);
-#pragma unroll
-                  for (int p = 0; p < NS; ++p)
-                    *(u32x2*)(Bs + p * BN * ROWB + lds_off<false, true>(n, kq >> 1) + (kq & 1) * 8) = parts[p];
-                }
+                for (int p = 0; p < NS; ++p)
+                  *(u32x2*)(Bs + p * BN * ROWB + lds_off<false, true>(n, kq >> 1) + (kq & 1) * 8) = parts[p];
               }
             }
           }
         };
-        auto step = [&](int bsel) {
+        auto fence = [] { __builtin_amdgcn_sched_barrier(0); };
+
+        // Software pipeline with one barrier per step: while step s is
+        // multiplied out of LDS buffer s % 2, step s + 1 (in registers) is
+        // split into buffer (s + 1) % 2 and step s + 2 is fetched.
+        prep(W.k0);
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) load_unit(i);
+        if (klim < kBK) mask_regs();
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) store_unit(0, i);
+        prep(W.k0 + kBK);
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) load_unit(i);
+        __syncthreads();
+        int bsel = 0;
+        for (int kk = W.k0; kk < W.k1; kk += kBK) {
+          if (klim < kBK) mask_regs();
           const char* As = lds + bsel * (A_BYTES + B_BYTES);
           const char* Bs = As + A_BYTES;
           if constexpr (F32) {
@@ -219,6 +259,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
               for (int a = 0; a < FM; ++a) fa[a] = *(const f32x4*)(As + lds_off<true>(wr + a * 32 + l32, 2 * s + lh));
 #pragma unroll
               for (int b = 0; b < FN; ++b) fb[b] = *(const f32x4*)(Bs + lds_off<true, true>(wc + b * 32 + l32, 2 * s + lh));
+              if (s == 0) {
+#pragma unroll
+                for (int i = 0; i < NLD; ++i) store_unit(bsel ^ 1, i);
+                prep(kk + 2 * kBK);
+#pragma unroll
+                for (int i = 0; i < NLD; ++i) load_unit(i);
+              }
 #pragma unroll
               for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -227,55 +274,67 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
                   for (int j = 0; j < 4; ++j) acc[a][b] = mfma_f32(fa[a][j], fb[b][j], acc[a][b]);
             }
           } else {
-            // two k-halves of 16; lane half lh reads chunk 2*kh + lh; only one
-            // half's fragments are live at a time
+            // Two k-halves of 16; lane half lh reads 16-byte chunk 2*kh + lh.
+            // The order is fixed by hand (sched_barrier fences): the first
+            // half's blocks each followed by a share of the next step's
+            // split-and-store, the second half's A fragments read as soon as
+            // the first half's die, then the second half's blocks each
+            // followed by a share of the fetch of the step after next.
+            auto frag_a = [&](int kh, int a, bf16x8(&f)[NS]) {
 #pragma unroll
-            for (int kh = 0; kh < 2; ++kh) {
-              bf16x8 fa[FM][NS], fb[FN][NS];
+              for (int p = 0; p < NS; ++p)
+                f[p] = *(const bf16x8*)(As + p * BM * ROWB + lds_off<false>(wr + a * 32 + l32, 2 * kh + lh));
+            };
+            auto frag_b = [&](int kh, int b, bf16x8(&f)[NS]) {
 #pragma unroll
-              for (int a = 0; a < FM; ++a)
+              for (int p = 0; p < NS; ++p)
+                f[p] = *(const bf16x8*)(Bs + p * BN * ROWB + lds_off<false, true>(wc + b * 32 + l32, 2 * kh + lh));
+            };
+            auto mma = [&](int a, int b, const bf16x8(&x)[NS], const bf16x8(&y)[NS]) {
+              f32x16 c = acc[a][b];
+              if constexpr (NS == 2) {
+                c = mfma_bf16(x[1], y[0], c);
+                c = mfma_bf16(x[0], y[1], c);
+                c = mfma_bf16(x[0], y[0], c);
+              } else {
+                c = mfma_bf16(x[2], y[0], c);
+                c = mfma_bf16(x[0], y[2], c);
+                c = mfma_bf16(x[1], y[1], c);
+                c = mfma_bf16(x[1], y[0], c);
+                c = mfma_bf16(x[0], y[1], c);
+                c = mfma_bf16(x[0], y[0], c);
+              }
+              acc[a][b] = c;
+            };
+            bf16x8 fa0[FM][NS], fb0[FN][NS], fa1[FM][NS], fb1[FN][NS];
 #pragma unroll
-                for (int p = 0; p < NS; ++p)
-                  fa[a][p] = *(const bf16x8*)(As + p * BM * ROWB + lds_off<false>(wr + a * 32 + l32, 2 * kh + lh));
+            for (int a = 0; a < FM; ++a) frag_a(0, a, fa0[a]);
 #pragma unroll
-              for (int b = 0; b < FN; ++b)
+            for (int b = 0; b < FN; ++b) frag_b(0, b, fb0[b]);
+            fence();
 #pragma unroll
-                for (int p = 0; p < NS; ++p)
-                  fb[b][p] = *(const bf16x8*)(Bs + p * BN * ROWB + lds_off<false, true>(wc + b * 32 + l32, 2 * kh + lh));
+            for (int blk = 0; blk < NB; ++blk) {
+              const int a = blk / FN, b = blk % FN;
+              mma(a, b, fa0[a], fb0[b]);
 #pragma unroll
-              for (int a = 0; a < FM; ++a)
+              for (int i = blk * NLD / NB; i < (blk + 1) * NLD / NB; ++i) store_unit(bsel ^ 1, i);
+              if (b == FN - 1) frag_a(1, a, fa1[a]);
+              fence();
+            }
 #pragma unroll
-                for (int b = 0; b < FN; ++b) {
-                  f32x16 c = acc[a][b];
-                  if constexpr (NS == 2) {
-                    c = mfma_bf16(fa[a][1], fb[b][0], c);
-                    c = mfma_bf16(fa[a][0], fb[b][1], c);
-                    c = mfma_bf16(fa[a][0], fb[b][0], c);
-                  } else {
-                    c = mfma_bf16(fa[a][2], fb[b][0], c);
-                    c = mfma_bf16(fa[a][0], fb[b][2], c);
-                    c = mfma_bf16(fa[a][1], fb[b][1], c);
-                    c = mfma_bf16(fa[a][1], fb[b][0], c);
-                    c = mfma_bf16(fa[a][0], fb[b][1], c);
-                    c = mfma_bf16(fa[a][0], fb[b][0], c);
-                  }
-                  acc[a][b] = c;
-                }
-              if (kh == 0) __builtin_amdgcn_sched_barrier(0);
+            for (int b = 0; b < FN; ++b) frag_b(1, b, fb1[b]);
+            prep(kk + 2 * kBK);
+            fence();
+#pragma unroll
+            for (int blk = 0; blk < NB; ++blk) {
+              const int a = blk / FN, b = blk % FN;
+              mma(a, b, fa1[a], fb1[b]);
+#pragma unroll
+              for (int i = blk * NLD / NB; i < (blk + 1) * NLD / NB; ++i) load_unit(i);
+              fence();
             }
           }
-        };
-
-        // Double-buffered LDS with one barrier per step: step s is split into
-        // buffer s % 2 while the loads of step s+1 are issued before the
-        // matrix-core work of step s.
-        if (W.k0 < W.k1) load(W.k0);
-        int bsel = 0;
-        for (int kk = W.k0; kk < W.k1; kk += kBK) {
-          store(bsel);
           __syncthreads();
-          if (kk + kBK < W.k1) load(kk + kBK);
-          step(bsel);
           bsel ^= 1;
         }
 

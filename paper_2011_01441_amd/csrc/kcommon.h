@@ -61,8 +61,10 @@ __device__ __forceinline__ WorkItem uni(const WorkItem& w) {
 // raw buffer loads outside that range return 0.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t rows,
                                                             int64_t ld, int64_t cols) {
-  int64_t bytes = rows > 0 ? ((rows - 1) * ld + cols) * 4 : 0;
-  if (bytes > 0xFFFFFFFFll) bytes = 0xFFFFFFFFll;
+  // branch-free: selects keep loops that rebuild resources in one block
+  int64_t bytes = ((rows - 1) * ld + cols) * 4;
+  bytes = rows > 0 ? bytes : 0;
+  bytes = bytes < 0xFFFFFFFFll ? bytes : 0xFFFFFFFFll;
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)(uint32_t)bytes,
                                            0x00020000);
 }

@@ -126,7 +126,7 @@ int choose_bool_tile(const std::vector<Piece>& pcs) {
 int choose_ring_tile(const std::vector<Piece>& pcs, int prec) {
   const int cand[4] = {RING_T256x256, RING_T256x128, RING_T128x128, RING_T128x64};
   const double eff[4] = {1.0, 1.1, 1.25, 1.6};
-  const int nc = prec == PREC_BF16X6 ? 3 : 4;
+  const int nc = prec == PREC_BF16X6 ? 3 : 4;   // no 256 x 256 for three parts
   return choose_tile(pcs, cand + (4 - nc), eff + (4 - nc), nc, [prec](int t, int& tm, int& tn) {
     RingTileShape s = ring_tile_shape(t, prec);
     tm = s.tm;
