@@ -250,7 +250,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps before timing (default: enough for about 0.3 s, so the "
+                         "clocks settle)")
     ap.add_argument("--workload", default="ring_longk", choices=sorted(WORKLOADS))
     ap.add_argument("--no-grid", action="store_true", help="skip the plain tile-grid baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -258,6 +260,9 @@ def main():
     ap.add_argument("--verify-rows", type=int, default=64)
     ap.add_argument("--no-server", action="store_true", help="skip the request-server runs")
     ap.add_argument("--server-requests", type=int, default=4096)
+    ap.add_argument("--hold", type=float, default=0.0,
+                    help="after the JSON line, keep running the step for this many seconds "
+                         "(for sampling clocks and power from outside)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -292,6 +297,10 @@ def main():
 
     # ---- PACO path
     res = None
+    if args.warmup is None:
+        call(ctx, w, Ad, Bd, C)
+        one = timed(torch, lambda: call(ctx, w, Ad, Bd, C), 1)
+        args.warmup = max(3, min(2000, int(math.ceil(0.3 / max(one, 1e-6)))))
     for _ in range(args.warmup):
         if w["kind"] == "strassen":
             call(ctx, w, Ad, Bd, C)
@@ -385,6 +394,10 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if args.hold > 0:
+        t_end = time.perf_counter() + args.hold
+        while time.perf_counter() < t_end:
+            timed(torch, lambda: call(ctx, w, Ad, Bd, C), 50)
     ctx.close()
 
 
