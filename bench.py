@@ -319,21 +319,27 @@ def main():
     achieved = work / (kern_ms * 1e-3) / 1e12
     value = classic_ops(w) / (ms * 1e-3) / 1e9
 
-    # ---- plain tile grid (same microkernels), split-k autotuned
+    # ---- plain tile grid (same microkernels), tile shape and split-k autotuned
     grid = None
     if not args.no_grid and w["kind"] != "strassen":
+        tile_env = {"ring": "PACO_RING_TILE", "bool": "PACO_BOOL_TILE"}.get(w["kind"], "PACO_INT_TILE")
+        tiles = {"ring": (4, 0, 1, 2) if prec != "bf16x6" else (0, 1, 2)}.get(w["kind"], (0, 1, 2, 3))
         best = None
-        for sk in (1, 2, 4, 8, 16, 32, 64, 128):
-            f = (lambda sk=sk: call(ctx, w, Ad, Bd, C, part="grid", split_k=sk))
-            f()
-            t = timed(torch, f, 3) * 1e3
-            if best is None or t < best[1]:
-                best = (sk, t)
-        gms = timed(torch, lambda: call(ctx, w, Ad, Bd, C, part="grid", split_k=best[0]),
+        for tile in tiles:
+            os.environ[tile_env] = str(tile)
+            for sk in (1, 2, 4, 8, 16, 32, 64, 128):
+                f = (lambda sk=sk: call(ctx, w, Ad, Bd, C, part="grid", split_k=sk))
+                f()
+                t = timed(torch, f, 3) * 1e3
+                if best is None or t < best[2]:
+                    best = (tile, sk, t)
+        os.environ[tile_env] = str(best[0])
+        gms = timed(torch, lambda: call(ctx, w, Ad, Bd, C, part="grid", split_k=best[1]),
                     args.steps) * 1e3
+        del os.environ[tile_env]
         grid = {"value": classic_ops(w) / (gms * 1e-3) / 1e9, "ms_per_step": round(gms, 4),
-                "split_k": best[0]}
-        log(f"grid: {gms:.3f} ms/step (split_k {best[0]})")
+                "tile": best[0], "split_k": best[1]}
+        log(f"grid: {gms:.3f} ms/step (tile {best[0]}, split_k {best[1]})")
 
     # ---- accuracy of this result
     err = None

@@ -106,7 +106,10 @@ paco_status paco_create(paco_ctx* out, int device, uint64_t workspace_budget_byt
 paco_status paco_destroy(paco_ctx ctx);
 /* `stream` is a hipStream_t passed as an opaque pointer. */
 paco_status paco_set_stream(paco_ctx ctx, void* stream);
-/* Number of processors p used by default: the device's compute units. */
+/* The device's compute units.  The default processor count of a PACO call
+ * is this times the number of workgroups of the chosen kernel that fit on
+ * one compute unit at once (1 for the matrix-core ring kernel, 2-4 for the
+ * VALU kernels); paco_mm_result.p reports the value used. */
 int paco_num_cus(paco_ctx ctx);
 const char* paco_status_string(paco_status s);
 const char* paco_last_error(paco_ctx ctx);
@@ -129,7 +132,8 @@ typedef struct paco_mm_desc {
   int32_t accumulate;           /* nonzero: C <- C (+) A (x) B */
   paco_precision precision;     /* ring only */
   paco_part_mode part;
-  int32_t p;                    /* processors (workgroups); 0 = compute units */
+  int32_t p;                    /* processors (workgroups); 0 = compute units
+                                   x resident workgroups per compute unit */
   int32_t grid_split_k;         /* GRID mode split-k; 0 = autotuned */
   int32_t verify_rows;          /* >0: float64 check of this many sampled
                                    rows on the GPU (ring only); the call

@@ -308,6 +308,15 @@ struct Norm {  // normalised call
 
 namespace paco {
 
+// Tile override for experiments (PACO_*_TILE = index into the kernel's tile
+// list); out-of-range values are ignored.
+static int env_tile(const char* name, int count, int dflt) {
+  const char* v = getenv(name);
+  if (!v) return dflt;
+  int t = atoi(v);
+  return (t >= 0 && t < count) ? t : dflt;
+}
+
 // Host part of a semiring MM plan: partition, tile choice, work lists.
 void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
                   int num_cus, DevPlan* np, double kcut_cost) {
@@ -318,31 +327,83 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
   int tile = 0, tm = 0, tn = 0, bk = 32;
   if (part == PACO_PART_PACO) {
     PartOpts po;
-    po.p = p;
     po.kcut_cost = kcut_cost;
     if (fam == 1) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
     else if (fam == 2) { po.q[0] = 16; po.q[1] = 16; po.q[2] = 32; }
-    pcs = partition_mm1(n, m, k, po);
-    if (fam == 1)  // bits -> words in m
-      for (Piece& pc : pcs) { pc.m0 /= 32; pc.m1 = words(pc.m1); }
-    if (fam == 0) tile = choose_int_tile(pcs);
-    else if (fam == 1) tile = choose_bool_tile(pcs);
-    else tile = choose_ring_tile(pcs, prec);
-    if (fam == 2 && getenv("PACO_RING_TILE")) tile = atoi(getenv("PACO_RING_TILE"));
+    auto part_for = [&](int pp) {
+      po.p = pp;
+      std::vector<Piece> v = partition_mm1(n, m, k, po);
+      if (fam == 1)  // bits -> words in m
+        for (Piece& pc : v) { pc.m0 /= 32; pc.m1 = words(pc.m1); }
+      return v;
+    };
+    const char* tile_env = fam == 0 ? "PACO_INT_TILE" : (fam == 1 ? "PACO_BOOL_TILE" : "PACO_RING_TILE");
+    if (p <= 0 && fam != 2) {
+      // Default p of the VALU kernels: one processor per workgroup slot.  A
+      // single workgroup per compute unit leaves each SIMD one wave to hide
+      // latency with, so each candidate tile is tried with p = CUs x (its
+      // resident workgroups per CU) -- when the problem is large enough to
+      // give every slot a few tiles -- and the (tile, p) with the shortest
+      // critical path wins: the worst piece's padded work, times the
+      // workgroups sharing its CU, times the tile's measured cost per
+      // element at that occupancy.
+      const int nc = 4;
+      const int ci[4] = {INT_T128x128, INT_T256x64, INT_T64x128, INT_T64x64};
+      const double ei[4] = {1.0, 1.14, 1.05, 0.95};
+      const int cb[4] = {BOOL_T512x32W, BOOL_T128x128W, BOOL_T256x64W, BOOL_T64x64W};
+      const double eb[4] = {1.0, 1.0, 0.98, 1.08};
+      const int forced = env_tile(tile_env, 4, -1);
+      const double work = (double)n * (double)mu * (double)k;
+      double bestc = 1e300;
+      for (int c = 0; c < nc; ++c) {
+        const int t = fam == 0 ? ci[c] : cb[c];
+        if (forced >= 0 && t != forced) continue;
+        int tm_, tn_;
+        if (fam == 0) { IntTileShape ts = int_tile_shape(t); tm_ = ts.tm; tn_ = ts.tn; }
+        else { BoolTileShape ts = bool_tile_shape(t); tm_ = ts.tm; tn_ = ts.tnw; }
+        int occ = fam == 0 ? int_occupancy(sr, t) : bool_occupancy(t);
+        occ = std::min(std::max(occ, 1), 8);
+        const double tile_work = (double)tm_ * tn_ * 256;   // one tile, 256 deep
+        const int pt = (occ > 1 && work >= (double)num_cus * occ * 4 * tile_work) ? num_cus * occ : num_cus;
+        std::vector<Piece> v = part_for(pt);
+        double worst = 0;
+        for (const Piece& pc : v) {
+          if (pc.empty()) continue;
+          const double tl = (double)((pc.n1 - pc.n0 + tm_ - 1) / tm_) * (double)((pc.m1 - pc.m0 + tn_ - 1) / tn_);
+          worst = std::max(worst, tl * tm_ * tn_ * (double)(pc.k1 - pc.k0));
+        }
+        const double cost = worst * ((double)pt / num_cus) * (fam == 0 ? ei[c] : eb[c]);
+        if (cost < bestc) {
+          bestc = cost;
+          tile = t;
+          p = pt;
+          pcs = std::move(v);
+        }
+      }
+    } else {
+      if (p <= 0) p = num_cus;
+      pcs = part_for(p);
+      if (fam == 0) tile = choose_int_tile(pcs);
+      else if (fam == 1) tile = choose_bool_tile(pcs);
+      else tile = choose_ring_tile(pcs, prec);
+      tile = env_tile(tile_env, fam == 2 ? 5 : 4, tile);
+    }
   } else {
     if (fam == 0) {
       tile = m <= 64 ? INT_T256x64 : (n <= 64 ? INT_T64x128 : INT_T128x128);
+      tile = env_tile("PACO_INT_TILE", 4, tile);
       IntTileShape ts = int_tile_shape(tile);
       tm = ts.tm; tn = ts.tn;
     } else if (fam == 1) {
       tile = BOOL_T128x128W;
+      tile = env_tile("PACO_BOOL_TILE", 4, tile);
       BoolTileShape ts = bool_tile_shape(tile);
       tm = ts.tm; tn = ts.tnw * 32;
     } else {
       // the largest tile the output fills (the same microkernels PACO uses)
       tile = (n >= 256 && m >= 256 && prec != PREC_BF16X6) ? RING_T256x256
              : (n >= 256 ? RING_T256x128 : (m >= 128 ? RING_T128x128 : RING_T128x64));
-      if (getenv("PACO_RING_TILE")) tile = atoi(getenv("PACO_RING_TILE"));
+      tile = env_tile("PACO_RING_TILE", 5, tile);
       RingTileShape ts = ring_tile_shape(tile, prec);
       tm = ts.tm; tn = ts.tn; bk = ts.bk;
     }
@@ -494,7 +555,7 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
     if (d->precision == PACO_PREC_AUTO) z.prec = auto_precision(z.k);
     else z.prec = (int)d->precision;
   }
-  const int p = d->p > 0 ? d->p : ctx->num_cus;
+  const int p = d->p > 0 ? d->p : (d->part == PACO_PART_PACO ? 0 : ctx->num_cus);
   if (p > 65536) {
     set_err(ctx, "p above 65536");
     return PACO_ERR_INVALID_ARG;
@@ -503,8 +564,10 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   // ---- plan
   char key[256];
   const double kc = d->kcut_cost > 0 ? d->kcut_cost : default_kcut_cost((int)d->sr);
-  snprintf(key, sizeof key, "mm/%d/%lld/%lld/%lld/%d/%d/%d/%d/%g", (int)d->sr, (long long)z.n,
-           (long long)z.m, (long long)z.k, (int)d->part, p, d->grid_split_k, z.prec, kc);
+  const char* tenv = getenv(is_bool ? "PACO_BOOL_TILE" : (d->sr == PACO_SR_PLUS_TIMES_F32 ? "PACO_RING_TILE"
+                                                                                           : "PACO_INT_TILE"));
+  snprintf(key, sizeof key, "mm/%d/%lld/%lld/%lld/%d/%d/%d/%d/%g/%.8s", (int)d->sr, (long long)z.n,
+           (long long)z.m, (long long)z.k, (int)d->part, p, d->grid_split_k, z.prec, kc, tenv ? tenv : "");
   DevPlan* dp = nullptr;
   auto itp = ctx->plans.find(key);
   if (itp != ctx->plans.end()) {
@@ -553,7 +616,7 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   }
   if (res) {
     res->precision = (paco_precision)(z.prec < 0 ? PACO_PREC_FP32 : z.prec);
-    res->p = d->part == PACO_PART_PACO ? p : dp->h.nwg;
+    res->p = d->part == PACO_PART_PACO ? dp->p : dp->h.nwg;
     res->n_pieces = dp->h.n_pieces;
     res->max_piece_volume = dp->h.vmax;
     res->min_piece_volume = dp->h.vmin;

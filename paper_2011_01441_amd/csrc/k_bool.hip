@@ -153,6 +153,26 @@ __global__ __launch_bounds__(kThreads) void k_semiring_bool(ProbRef pr, const Wo
 
 }  // namespace
 
+int bool_occupancy(int tile) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (tile) {
+    case BOOL_T512x32W:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_bool<512, 32, 8, 8>, kThreads, 0);
+      break;
+    case BOOL_T128x128W:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_bool<128, 128, 8, 8>, kThreads, 0);
+      break;
+    case BOOL_T256x64W:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_bool<256, 64, 8, 8>, kThreads, 0);
+      break;
+    case BOOL_T64x64W:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_bool<64, 64, 4, 4>, kThreads, 0);
+      break;
+  }
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
 BoolTileShape bool_tile_shape(int tile) {
   switch (tile) {
     case BOOL_T512x32W: return {512, 32};

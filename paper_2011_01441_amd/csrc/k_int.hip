@@ -195,7 +195,32 @@ hipError_t launch_op(int tile, const ProbRef& pr, const WorkItem* items, const i
   return hipGetLastError();
 }
 
+template <class Op>
+int occupancy_op(int tile) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (tile) {
+    case INT_T128x128:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 128, 128, 8, 8>, kThreads, 0);
+      break;
+    case INT_T256x64:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 256, 64, 8, 8>, kThreads, 0);
+      break;
+    case INT_T64x64:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 64, 64, 4, 4>, kThreads, 0);
+      break;
+    case INT_T64x128:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 64, 128, 4, 8>, kThreads, 0);
+      break;
+  }
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
 }  // namespace
+
+int int_occupancy(int sr, int tile) {
+  return sr == SR_MAXPLUS ? occupancy_op<OpMax>(tile) : occupancy_op<OpMin>(tile);
+}
 
 IntTileShape int_tile_shape(int tile) {
   switch (tile) {

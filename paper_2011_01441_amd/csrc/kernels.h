@@ -11,6 +11,9 @@ namespace paco {
 enum IntTile : int { INT_T128x128 = 0, INT_T256x64 = 1, INT_T64x64 = 2, INT_T64x128 = 3 };
 struct IntTileShape { int tm, tn; };
 IntTileShape int_tile_shape(int tile);
+// Workgroups of the kernel that fit on one compute unit at once (1 when the
+// runtime cannot tell, e.g. without a device).
+int int_occupancy(int sr, int tile);
 
 // Persistent semiring kernel: `nwg` workgroups; workgroup w runs the items
 // wg_off[q] .. wg_off[q+1] of processor q = remap(w).
@@ -23,6 +26,7 @@ hipError_t launch_semiring_int(int sr, int tile, const ProbRef& pr, const WorkIt
 enum BoolTile : int { BOOL_T512x32W = 0, BOOL_T128x128W = 1, BOOL_T256x64W = 2, BOOL_T64x64W = 3 };
 struct BoolTileShape { int tm, tnw; };
 BoolTileShape bool_tile_shape(int tile);
+int bool_occupancy(int tile);
 hipError_t launch_semiring_bool(int tile, const ProbRef& pr, const WorkItem* items,
                                 const int32_t* wg_off, int nwg, int xcd_remap, void* ws,
                                 hipStream_t s);

@@ -9,7 +9,7 @@ import collections
 import numpy as np
 import pytest
 
-P = pytest.importorskip("paper_2011_01441_amd")
+import paper_2011_01441_amd as P  # noqa: E402
 
 
 def _reqs(count, seed, lo=32, hi=4096):

@@ -10,7 +10,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-P = pytest.importorskip("paper_2011_01441_amd")
+import paper_2011_01441_amd as P  # noqa: E402
 DEV = torch.device("cuda:0")
 
 
@@ -45,7 +45,9 @@ def test_minplus_config0_bit_exact(ctx):
     A, B = workloads.minplus_operands(384, 256, 320, seed=0)
     C, res = ctx.semiring_mm(dev(A), dev(B), "minplus", return_result=True)
     assert np.array_equal(host(C), oracle.minplus(A, B))
-    assert res["n_pieces"] == 256 and res["n_kcuts"] > 0
+    # default p: one processor per resident workgroup slot (a multiple of the CUs)
+    cus = P.lib().paco_num_cus(ctx._h)
+    assert res["p"] % cus == 0 and res["n_pieces"] == res["p"] and res["n_kcuts"] > 0
 
 
 @pytest.mark.parametrize("n,m,k", [(1, 1, 1), (5, 3, 2), (97, 130, 75), (300, 77, 129), (64, 64, 1000)])

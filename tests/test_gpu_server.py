@@ -11,7 +11,7 @@ import oracle
 import workloads
 
 pytestmark = pytest.mark.gpu
-P = pytest.importorskip("paper_2011_01441_amd")
+import paper_2011_01441_amd as P  # noqa: E402
 DEV = torch.device("cuda:0")
 
 

@@ -11,7 +11,7 @@ import os
 import numpy as np
 import pytest
 
-P = pytest.importorskip("paper_2011_01441_amd")
+import paper_2011_01441_amd as P  # noqa: E402
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
