@@ -143,7 +143,9 @@ typedef struct paco_mm_desc {
                                    the virtual cuboid is chosen, k counts as
                                    k / kcut_cost (1 = the paper's rule; a
                                    k-cut costs a temporary face written and
-                                   read back); 0 = library default */
+                                   read back); 0 = library default: 16
+                                   for the ring, chosen among 1, 4 and 16
+                                   with the tile and p for the others */
 } paco_mm_desc;
 
 typedef struct paco_mm_result {
@@ -155,6 +157,7 @@ typedef struct paco_mm_result {
   int32_t n_kcuts;              /* pieces writing a temporary face */
   double verify_max_rel;        /* max |C-C64| / (|A||B|) over sampled rows, -1 if not verified */
   double verify_max_abs;        /* max |C-C64| over sampled rows */
+  double kcut_cost;             /* k-cut cost the PACO partition used */
 } paco_mm_result;
 
 /* Extended form: explicit leading dimensions, accumulation, precision,

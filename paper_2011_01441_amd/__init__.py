@@ -49,7 +49,8 @@ class MMResult(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("p", ctypes.c_int32), ("n_pieces", ctypes.c_int32),
                 ("max_piece_volume", ctypes.c_int64), ("min_piece_volume", ctypes.c_int64),
                 ("temp_elems", ctypes.c_int64), ("n_kcuts", ctypes.c_int32),
-                ("verify_max_rel", ctypes.c_double), ("verify_max_abs", ctypes.c_double)]
+                ("verify_max_rel", ctypes.c_double), ("verify_max_abs", ctypes.c_double),
+                ("kcut_cost", ctypes.c_double)]
 
 
 class Piece(ctypes.Structure):

@@ -277,6 +277,14 @@ double default_kcut_cost(int sr) {
   return sr == PACO_SR_PLUS_TIMES_F32 ? 16.0 : 1.0;
 }
 
+// k-cut cost a PACO call plans with when the caller gives none: the
+// environment override, else 16 for the ring; 0 (choose among 1, 4 and 16
+// with the tile and p) for the VALU semirings.
+double plan_kcut_cost(int sr) {
+  if (getenv("PACO_KCUT_COST") || sr == PACO_SR_PLUS_TIMES_F32) return default_kcut_cost(sr);
+  return 0.0;
+}
+
 int64_t words(int64_t bits) { return (bits + 31) / 32; }
 
 // Float32 componentwise-error model of bf16x3 at depth k (see paco.h, AUTO).
@@ -325,6 +333,7 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
   const int fam = sr == PACO_SR_PLUS_TIMES_F32 ? 2 : (is_bool ? 1 : 0);
   std::vector<Piece> pcs;
   int tile = 0, tm = 0, tn = 0, bk = 32;
+  double kcut_cost_used = 0.0;
   if (part == PACO_PART_PACO) {
     PartOpts po;
     po.kcut_cost = kcut_cost;
@@ -339,49 +348,77 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
     };
     const char* tile_env = fam == 0 ? "PACO_INT_TILE" : (fam == 1 ? "PACO_BOOL_TILE" : "PACO_RING_TILE");
     if (p <= 0 && fam != 2) {
-      // Default p of the VALU kernels: one processor per workgroup slot.  A
-      // single workgroup per compute unit leaves each SIMD one wave to hide
-      // latency with, so each candidate tile is tried with p = CUs x (its
-      // resident workgroups per CU) -- when the problem is large enough to
-      // give every slot a few tiles -- and the (tile, p) with the shortest
-      // critical path wins: the worst piece's padded work, times the
-      // workgroups sharing its CU, times the tile's measured cost per
-      // element at that occupancy.
-      const int nc = 4;
+      // Default p of the VALU kernels.  A single workgroup per compute unit
+      // leaves each SIMD one wave to hide latency with, so a processor is a
+      // workgroup slot: each candidate tile is tried with p = CUs x (its
+      // resident workgroups per CU) -- when the problem gives every slot a
+      // few tiles -- and with four times as many pieces as slots, which the
+      // hardware dispatcher hands to slots as they free up (one piece per
+      // slot measured about 15% slower: the slots do not run at one speed,
+      // the XCD clocks alone differ by 3%).  Unless the caller fixed it, the
+      // k-cut cost is tried at 1 (the paper's rule), 4, 16 and 64.  The
+      // plan with the shortest estimated time wins: the worst piece's
+      // padded tiles, each costing its k-range plus a fixed
+      // prologue/epilogue overhead, at the tile's measured rate per compute
+      // unit shared by the workgroups on it, times the rounds of pieces per
+      // slot, plus the temporary faces written and read back at HBM speed.
+      // These kernels stream about 8 elements per byte, so a k-cut also
+      // costs L2 reuse (concurrent pieces no longer walk k in step); the
+      // overhead term and the face traffic stand for that.
       const int ci[4] = {INT_T128x128, INT_T256x64, INT_T64x128, INT_T64x64};
       const double ei[4] = {1.0, 1.14, 1.05, 0.95};
       const int cb[4] = {BOOL_T512x32W, BOOL_T128x128W, BOOL_T256x64W, BOOL_T64x64W};
       const double eb[4] = {1.0, 1.0, 0.98, 1.08};
+      const double rate_cu = fam == 0 ? 70e9 : 110e9;      // elements (words) per second per CU
+      const double k_ovh = fam == 0 ? 64.0 : 128.0;        // prologue + epilogue, in k units
+      const double kcs[4] = {1.0, 4.0, 16.0, 64.0};
+      const int nkc = kcut_cost > 0 ? 1 : 4;
       const int forced = env_tile(tile_env, 4, -1);
       const double work = (double)n * (double)mu * (double)k;
       double bestc = 1e300;
-      for (int c = 0; c < nc; ++c) {
-        const int t = fam == 0 ? ci[c] : cb[c];
-        if (forced >= 0 && t != forced) continue;
-        int tm_, tn_;
-        if (fam == 0) { IntTileShape ts = int_tile_shape(t); tm_ = ts.tm; tn_ = ts.tn; }
-        else { BoolTileShape ts = bool_tile_shape(t); tm_ = ts.tm; tn_ = ts.tnw; }
-        int occ = fam == 0 ? int_occupancy(sr, t) : bool_occupancy(t);
-        occ = std::min(std::max(occ, 1), 8);
-        const double tile_work = (double)tm_ * tn_ * 256;   // one tile, 256 deep
-        const int pt = (occ > 1 && work >= (double)num_cus * occ * 4 * tile_work) ? num_cus * occ : num_cus;
-        std::vector<Piece> v = part_for(pt);
-        double worst = 0;
-        for (const Piece& pc : v) {
-          if (pc.empty()) continue;
-          const double tl = (double)((pc.n1 - pc.n0 + tm_ - 1) / tm_) * (double)((pc.m1 - pc.m0 + tn_ - 1) / tn_);
-          worst = std::max(worst, tl * tm_ * tn_ * (double)(pc.k1 - pc.k0));
-        }
-        const double cost = worst * ((double)pt / num_cus) * (fam == 0 ? ei[c] : eb[c]);
-        if (cost < bestc) {
-          bestc = cost;
-          tile = t;
-          p = pt;
-          pcs = std::move(v);
+      for (int ik = 0; ik < nkc; ++ik) {
+        po.kcut_cost = kcut_cost > 0 ? kcut_cost : kcs[ik];
+        for (int c = 0; c < 4; ++c) {
+          const int t = fam == 0 ? ci[c] : cb[c];
+          if (forced >= 0 && t != forced) continue;
+          int tm_, tn_;
+          if (fam == 0) { IntTileShape ts = int_tile_shape(t); tm_ = ts.tm; tn_ = ts.tn; }
+          else { BoolTileShape ts = bool_tile_shape(t); tm_ = ts.tm; tn_ = ts.tnw; }
+          int occ = fam == 0 ? int_occupancy(sr, t) : bool_occupancy(t);
+          occ = std::min(std::max(occ, 1), 8);
+          const double tile_work = (double)tm_ * tn_ * 256;   // one tile, 256 deep
+          const int slots = (occ > 1 && work >= (double)num_cus * occ * 4 * tile_work) ? num_cus * occ : num_cus;
+          for (int f : {1, 4}) {
+            const int pt = slots * f;
+            if (f > 1 && work < (double)pt * 4 * tile_work) continue;
+            if (pt > 65536) continue;
+            std::vector<Piece> v = part_for(pt);
+            double worst = 0, temps = 0;
+            for (const Piece& pc : v) {
+              if (pc.empty()) continue;
+              const double tl =
+                  (double)((pc.n1 - pc.n0 + tm_ - 1) / tm_) * (double)((pc.m1 - pc.m0 + tn_ - 1) / tn_);
+              worst = std::max(worst, tl * tm_ * tn_ * ((double)(pc.k1 - pc.k0) + k_ovh));
+              if (pc.k0 > 0) temps += (double)(pc.n1 - pc.n0) * (double)(pc.m1 - pc.m0);  // upper k-part
+            }
+            const double rounds = (double)pt / slots;
+            const double cost = worst * ((double)slots / num_cus) * rounds * (fam == 0 ? ei[c] : eb[c]) /
+                                    rate_cu * (f == 1 ? 1.15 : 1.0) +
+                                temps * 8.0 / 5e12;
+            if (cost < bestc) {
+              bestc = cost;
+              tile = t;
+              p = pt;
+              kcut_cost_used = po.kcut_cost;
+              pcs = std::move(v);
+            }
+          }
         }
       }
     } else {
       if (p <= 0) p = num_cus;
+      if (kcut_cost <= 0) po.kcut_cost = 1.0;
+      kcut_cost_used = po.kcut_cost;
       pcs = part_for(p);
       if (fam == 0) tile = choose_int_tile(pcs);
       else if (fam == 1) tile = choose_bool_tile(pcs);
@@ -423,6 +460,7 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
   np->tile = tile;
   np->fam = fam;
   np->p = p;
+  np->kcut = kcut_cost_used;
 }
 
 }  // namespace paco
@@ -563,7 +601,8 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
 
   // ---- plan
   char key[256];
-  const double kc = d->kcut_cost > 0 ? d->kcut_cost : default_kcut_cost((int)d->sr);
+  // 0 = chosen with the tile and p (VALU semirings, see make_mm_plan)
+  const double kc = d->kcut_cost > 0 ? d->kcut_cost : plan_kcut_cost((int)d->sr);
   const char* tenv = getenv(is_bool ? "PACO_BOOL_TILE" : (d->sr == PACO_SR_PLUS_TIMES_F32 ? "PACO_RING_TILE"
                                                                                            : "PACO_INT_TILE"));
   snprintf(key, sizeof key, "mm/%d/%lld/%lld/%lld/%d/%d/%d/%d/%g/%.8s", (int)d->sr, (long long)z.n,
@@ -622,6 +661,7 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
     res->min_piece_volume = dp->h.vmin;
     res->temp_elems = dp->h.temp_elems;
     res->n_kcuts = dp->h.n_kcuts;
+    res->kcut_cost = dp->kcut;
   }
   if (d->verify_rows > 0) {
     st = verify_sampled(ctx, z.n, z.m, z.k, (const float*)d->A, z.lda, (const float*)d->B, z.ldb,

@@ -19,6 +19,7 @@ struct DevPlan {
   int tile = 0;
   int fam = 0;  // 0 integer VALU, 1 boolean, 2 ring
   int p = 0;
+  double kcut = 0.0;   // k-cut cost the partition used (PACO mode)
   WorkItem* d_items = nullptr;
   int32_t* d_wg_off = nullptr;
   RedTile* d_tiles = nullptr;
@@ -71,6 +72,7 @@ bool ring_vec_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t
 void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
                   int num_cus, DevPlan* np, double kcut_cost);
 double default_kcut_cost(int sr);
+double plan_kcut_cost(int sr);
 
 // Brackets one kernel launch with timing events when timing is enabled.
 struct TimeScope {
