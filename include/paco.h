@@ -234,7 +234,10 @@ paco_status paco_partition(int64_t n, int64_t m, int64_t k, const paco_part_opts
                            paco_piece* out, int64_t cap, int64_t* n_out);
 
 /* Host-only introspection of the plan a semiring MM call launches (for
- * tests and tools; no device is touched).  Call once with all arrays NULL
+ * tests and tools; no device memory is touched).  p = 0 (PACO mode) makes
+ * the default choice of a call with p = 0, using the runtime's occupancy
+ * figures where a device is present and 1 workgroup per compute unit
+ * otherwise.  Call once with all arrays NULL
  * to get the sizes in *info, then again with arrays of at least those sizes
  * (the counts in *info on input are the capacities):
  *   items : n_items x 8 int64 (prob, n0, n1, m0, m1, k0, k1, out_off), in

@@ -471,12 +471,17 @@ extern "C" paco_status paco_plan_export(int64_t n, int64_t m, int64_t k, paco_se
                                         int64_t* srcs) {
   if (!info || n <= 0 || m <= 0 || k <= 0 || n >= (1ll << 31) || m >= (1ll << 31) || k >= (1ll << 31) ||
       sr < PACO_SR_PLUS_TIMES_F32 || sr > PACO_SR_OR_AND_B1 || part < PACO_PART_PACO || part > PACO_PART_GRID ||
-      p < 1 || p > 65536 || split_k < 0 || num_cus < 1 || prec < PACO_PREC_FP32 || prec > PACO_PREC_AUTO)
+      p < 0 || (p == 0 && part != PACO_PART_PACO) || p > 65536 || split_k < 0 || num_cus < 1 ||
+      prec < PACO_PREC_FP32 || prec > PACO_PREC_AUTO)
     return PACO_ERR_INVALID_ARG;
   int pr = -1;
   if (sr == PACO_SR_PLUS_TIMES_F32) pr = prec == PACO_PREC_AUTO ? auto_precision(k) : (int)prec;
   DevPlan dp;
-  make_mm_plan((int)sr, n, m, k, (int)part, p, split_k, pr, num_cus, &dp, default_kcut_cost((int)sr));
+  // p = 0: the default choice of a call (p, tile and, for the VALU
+  // semirings, the k-cut cost); occupancies come from the runtime, 1 where
+  // it has no device
+  make_mm_plan((int)sr, n, m, k, (int)part, p, split_k, pr, num_cus, &dp,
+               p == 0 ? plan_kcut_cost((int)sr) : default_kcut_cost((int)sr));
   const HostPlan& h = dp.h;
   const bool fill = items && wg_off && tiles && srcs;
   if (fill) {

@@ -109,3 +109,19 @@ def test_ring_default_kcut_cost_prefers_n_and_m_cuts():
     items, *_ = P.plan_export(2048, 1024, 65536, "ring", p=256, precision="bf16x3")
     ext = items[:, [2, 4, 6]] - items[:, [1, 3, 5]]
     assert (ext == [256, 256, 8192]).all()
+
+
+@pytest.mark.parametrize("sr,n,m,k", [("minplus", 384, 256, 320), ("minplus", 700, 300, 2048),
+                                      ("maxplus", 4096, 64, 512), ("maxplus", 257, 513, 129)])
+def test_default_choice_plan_replay(sr, n, m, k):
+    """p = 0: the call's default choice of processor count, tile and k-cut
+    cost still yields a plan that covers every (i, j, l) once."""
+    if sr == "minplus":
+        A, B = workloads.minplus_operands(n, m, k, seed=5)
+        ref = oracle.minplus(A, B)
+    else:
+        A, B = workloads.maxplus_operands(n, m, k, seed=5)
+        ref = oracle.maxplus(A, B)
+    C, info = replay(sr, A, B, n, m, k, part="paco", p=0)
+    np.testing.assert_array_equal(C, ref)
+    assert info["n_wg"] % 256 == 0   # slots (or 4x slots) of 256 compute units
