@@ -42,8 +42,12 @@ WORKLOADS = {
                         desc="(max,+) int32 A 131072x512, B 512x64, U[-2^15,2^15)"),
     "bool_c2b": dict(kind="bool", n=8192, m=8192, k=8192, density=0.05,
                      desc="boolean OR-AND 8192^3 bits, density 0.05, packed uint32"),
-    "strassen_c3": dict(kind="strassen", n=16384, levels=2, prec="bf16x3",
-                        desc="Strassen 2 levels, n=16384 f32 U[-1,1], bf16x3 leaf"),
+    "strassen_c3": dict(kind="strassen", n=16384, mode="pbfs", p=8, gamma=0, base=256, prec="bf16x3",
+                        desc="PACO Strassen, pruned BFS over 8 processor groups (one per XCD), "
+                             "n=16384 f32 U[-1,1], bf16x3 node products"),
+    "strassen_c3_levels2": dict(kind="strassen", n=16384, mode="levels", levels=2, prec="bf16x3",
+                                desc="Strassen 2 fixed levels, 49 leaves as one MM-1-Piece batch, "
+                                     "n=16384 f32 U[-1,1], bf16x3 leaf"),
 }
 
 
@@ -98,9 +102,13 @@ def algorithmic(w, prec):
     if kind in ("ring", "strassen"):
         if kind == "ring":
             nmk = w["n"] * w["m"] * w["k"]
-        else:
+        elif w["mode"] == "levels":
             h = w["n"] >> w["levels"]
             nmk = (7 ** w["levels"]) * h ** 3
+        else:   # the node products the pruned-BFS schedule hands out
+            import paper_2011_01441_amd as P
+            levels, _, _ = P.strassen_schedule(w["n"], w["p"], w["gamma"], w["base"])
+            nmk = sum(lv["assigned"] * lv["h"] ** 3 for lv in levels)
         mult = {"bf16x3": 3, "bf16x6": 6, "fp32": 1}[prec]
         flops = 2.0 * nmk * mult
         return flops, "TFLOP/s", "mfma", PEAK["fp32" if prec == "fp32" else "bf16"]
@@ -124,6 +132,8 @@ def classic_ops(w):
 def call(ctx, w, Ad, Bd, C, **kw):
     kind = w["kind"]
     if kind == "strassen":
+        if w["mode"] == "pbfs":
+            return ctx.strassen_pbfs(Ad, Bd, C=C, p=w["p"], gamma=w["gamma"], base=w["base"], leaf=w["prec"])
         return ctx.strassen_mm(Ad, Bd, levels=w["levels"], leaf=w["prec"], C=C)
     if kind == "bool":
         return ctx.semiring_mm(Ad, Bd, "bool", n=w["n"], m=w["m"], k=w["k"], C=C, **kw)
@@ -327,6 +337,16 @@ def main():
     achieved = work / (kern_ms * 1e-3) / 1e12
     value = classic_ops(w) / (ms * 1e-3) / 1e9
 
+    # ---- Strassen: the classic product on the same operands (PACO ring path)
+    classic = None
+    if not args.no_grid and w["kind"] == "strassen":
+        f = (lambda: ctx.semiring_mm(Ad, Bd, "ring", C=C, precision=w["prec"]))
+        for _ in range(3):
+            f()
+        cms = timed(torch, f, args.steps) * 1e3
+        classic = {"value": classic_ops(w) / (cms * 1e-3) / 1e9, "ms_per_step": round(cms, 4)}
+        log(f"classic product: {cms:.3f} ms/step")
+
     # ---- plain tile grid (same microkernels), tile shape and split-k autotuned
     grid = None
     if not args.no_grid and w["kind"] != "strassen":
@@ -404,6 +424,8 @@ def main():
                      "other_ms": round(other_ms, 4), "work_per_launch": work},
         "grid_baseline": grid,
         "paco_vs_grid": round(grid["ms_per_step"] / ms, 4) if grid else None,
+        "classic_baseline": classic,
+        "strassen_vs_classic": round(classic["ms_per_step"] / ms, 4) if classic else None,
         "error": err,
         "server": server,
         "cpu_baseline": cpu,

@@ -175,6 +175,65 @@ paco_status paco_semiring_mm_ex(paco_ctx ctx, const paco_mm_desc* d, paco_mm_res
 paco_status paco_strassen_mm(paco_ctx ctx, int64_t n, const float* A, const float* B,
                              float* C, int levels, paco_precision leaf);
 
+/* PACO Strassen with the pruned breadth-first schedule of section "PACO
+ * Strassen" (and its corollary Strassen-Const-Pieces).  The 7-way recursion
+ * tree is expanded depth by depth, with every S, T and M of a depth held in
+ * temporary space.  At a depth with N >= p unassigned nodes, floor(N/p)*p of
+ * them (the first in breadth-first order) are handed out, node i to
+ * processor i mod p, and the rest are divided again.  After `gamma`
+ * super-rounds (0: no limit), or when nodes would become smaller than `base`
+ * or of odd size, all remaining nodes are handed out round-robin.
+ *
+ * A processor here is a group of num_cus/p consecutive compute units (p = 8:
+ * one XCD with its own L2, the private cache of the paper's processor).  It
+ * runs each of its nodes as a classic product on the matrix-core kernel,
+ * split over the group's compute units by MM-1-Piece.  The paper runs an
+ * assigned node with sequential Strassen on one processor; here the node's
+ * size is the recursion cutoff.  All assigned nodes of all depths run in one
+ * persistent launch; pre-additions run before it and combines after it, both
+ * one depth at a time (the top min(first assigning depth, 3) levels fused).
+ *
+ * A, B, C: dense n-by-n float32 device pointers.  p in [1, compute units]
+ * (0 = compute units / 32, one per XCD).  base >= 1 (0 = 256).  leaf: ring
+ * precision of the node products (AUTO: bf16x3 when the first assigned
+ * nodes are at least 1024 wide, else bf16x6). */
+typedef struct paco_strassen_desc {
+  int64_t n;
+  const float* A;
+  const float* B;
+  float* C;
+  int32_t p;
+  int32_t gamma;
+  int64_t base;
+  paco_precision leaf;
+} paco_strassen_desc;
+
+typedef struct paco_strassen_result {
+  int32_t p;                 /* processors (groups of compute units) */
+  int32_t super_rounds;      /* depths that handed out floor(N/p)*p nodes */
+  int32_t max_depth;         /* deepest depth with assigned nodes */
+  int64_t nodes;             /* nodes handed out */
+  double max_work, min_work; /* per processor: sum of node n'^3 */
+  uint64_t temp_bytes;       /* S, T, M of all depths */
+  paco_precision leaf;
+} paco_strassen_result;
+
+paco_status paco_strassen_pbfs(paco_ctx ctx, const paco_strassen_desc* d, paco_strassen_result* out);
+
+/* Host-only: the schedule paco_strassen_pbfs runs.  levels[i] describes
+ * depth i (the node dimension h, the nodes of the depth, how many were
+ * handed out, whether the depth was a super-round); work_classic[j] and
+ * work_strassen[j] (optional, p entries) are processor j's sum of h^3 and of
+ * h^log2(7) over its nodes.  Call with cap = 0 to get *n_levels. */
+typedef struct paco_strassen_level {
+  int32_t depth, super_round;
+  int64_t h, nodes, assigned;
+} paco_strassen_level;
+
+paco_status paco_strassen_schedule(int64_t n, int32_t p, int32_t gamma, int64_t base,
+                                   paco_strassen_level* levels, int32_t cap, int32_t* n_levels,
+                                   double* work_classic, double* work_strassen);
+
 /* ----------------------------------------------------- float64 checker */
 
 /* For `nrows` rows listed in the device array `rows` (int64), compute on

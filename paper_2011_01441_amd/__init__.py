@@ -53,6 +53,23 @@ class MMResult(ctypes.Structure):
                 ("kcut_cost", ctypes.c_double)]
 
 
+class StrassenDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("p", ctypes.c_int32), ("gamma", ctypes.c_int32), ("base", ctypes.c_int64),
+                ("leaf", ctypes.c_int)]
+
+
+class StrassenResult(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("super_rounds", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("nodes", ctypes.c_int64), ("max_work", ctypes.c_double), ("min_work", ctypes.c_double),
+                ("temp_bytes", ctypes.c_uint64), ("leaf", ctypes.c_int)]
+
+
+class StrassenLevel(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("super_round", ctypes.c_int32), ("h", ctypes.c_int64),
+                ("nodes", ctypes.c_int64), ("assigned", ctypes.c_int64)]
+
+
 class Piece(ctypes.Structure):
     _fields_ = [("n0", ctypes.c_int64), ("n1", ctypes.c_int64), ("m0", ctypes.c_int64),
                 ("m1", ctypes.c_int64), ("k0", ctypes.c_int64), ("k1", ctypes.c_int64),
@@ -132,6 +149,10 @@ def lib():
     L.paco_semiring_mm.argtypes = [vp, i64, i64, i64, ci, vp, vp, vp]
     L.paco_semiring_mm_ex.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(MMResult)]
     L.paco_strassen_mm.argtypes = [vp, i64, vp, vp, vp, ci, ci]
+    L.paco_strassen_pbfs.argtypes = [vp, ctypes.POINTER(StrassenDesc), ctypes.POINTER(StrassenResult)]
+    L.paco_strassen_schedule.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, i64,
+                                         ctypes.POINTER(StrassenLevel), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32), vp, vp]
     L.paco_verify_rows_f64.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, i64,
                                        ctypes.POINTER(ctypes.c_double)]
     L.paco_partition.argtypes = [i64, i64, i64, ctypes.POINTER(PartOpts), ctypes.POINTER(Piece),
@@ -165,6 +186,23 @@ def _check(st, ctx=None):
         L = lib()
         msg = L.paco_last_error(ctx).decode() if ctx else ""
         raise PacoError(st, f"{L.paco_status_string(st).decode()}: {msg}")
+
+
+def strassen_schedule(n, p, gamma=0, base=256):
+    """Host-only: the pruned-BFS schedule of PACO Strassen.  Returns (levels,
+    work_classic, work_strassen): one dict per depth (depth, super_round, h,
+    nodes, assigned) and per-processor sums of h^3 and h^log2(7)."""
+    import numpy as np
+    L = lib()
+    nl = ctypes.c_int32()
+    _check(L.paco_strassen_schedule(n, p, gamma, base, None, 0, ctypes.byref(nl), None, None))
+    lv = (StrassenLevel * max(nl.value, 1))()
+    wc = np.zeros(p, np.float64)
+    wsr = np.zeros(p, np.float64)
+    _check(L.paco_strassen_schedule(n, p, gamma, base, lv, nl.value, ctypes.byref(nl),
+                                    ctypes.c_void_p(wc.ctypes.data), ctypes.c_void_p(wsr.ctypes.data)))
+    levels = [{f[0]: getattr(lv[i], f[0]) for f in StrassenLevel._fields_} for i in range(nl.value)]
+    return levels, wc, wsr
 
 
 def partition(n, m, k, p, q=(1, 1, 1), weights=None, multi_piece=False, kcut_cost=1.0):
@@ -290,6 +328,28 @@ class Context:
         _check(self._L.paco_strassen_mm(self._h, n, _ptr(A), _ptr(B), _ptr(C), levels,
                                         PRECISION[leaf]), self._h)
         return C
+
+    def strassen_pbfs(self, A, B, C=None, p=0, gamma=0, base=0, leaf="bf16x3", return_result=False):
+        """PACO Strassen with the pruned-BFS schedule over p processor groups
+        (0: one per XCD); gamma caps the super-rounds (0: none)."""
+        self._check_tensor(A, "A", torch.float32)
+        self._check_tensor(B, "B", torch.float32)
+        n = A.shape[0]
+        if A.shape != (n, n) or B.shape != (n, n) or not A.is_contiguous() or not B.is_contiguous():
+            raise ValueError("Strassen needs dense square operands of equal size")
+        if C is None:
+            C = torch.empty((n, n), dtype=torch.float32, device=A.device)
+        elif C.shape != (n, n) or not C.is_contiguous():
+            raise ValueError("C must be a dense n x n tensor")
+        d = StrassenDesc(n, _ptr(A), _ptr(B), _ptr(C), p, gamma, base, PRECISION[leaf])
+        r = StrassenResult()
+        self._stream()
+        _check(self._L.paco_strassen_pbfs(self._h, ctypes.byref(d), ctypes.byref(r)), self._h)
+        if not return_result:
+            return C
+        res = {f[0]: getattr(r, f[0]) for f in StrassenResult._fields_}
+        res["leaf"] = PRECISION_NAME.get(res["leaf"], res["leaf"])
+        return C, res
 
     def timing(self, enable=None):
         """timing(True) starts per-kernel event timing; timing() reads and

@@ -24,7 +24,7 @@ struct DevPlan {
   int32_t* d_wg_off = nullptr;
   RedTile* d_tiles = nullptr;
   RedSrc* d_srcs = nullptr;
-  ~DevPlan();
+  virtual ~DevPlan();
 };
 
 }  // namespace paco

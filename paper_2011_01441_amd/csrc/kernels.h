@@ -60,10 +60,18 @@ hipError_t launch_verify_f64(int64_t n, int64_t m, int64_t k, const float* A, in
                              const float* B, int64_t ldb, const float* C, int64_t ldc,
                              const int64_t* rows, int64_t nrows, double* part, hipStream_t s);
 
-// Strassen two-level fused pre-add and combine (see k_strassen.hip).
+// Strassen fused L-level (1..3) pre-add and combine (see k_strassen.hip):
+// n x n A, B -> 7^L S, T blocks of (n/2^L)^2; 7^L M blocks -> n x n C.
 hipError_t launch_strassen_preadd(int levels, int64_t n, const float* A, const float* B,
                                   float* S, float* T, hipStream_t s);
 hipError_t launch_strassen_combine(int levels, int64_t n, const float* M, float* C,
                                    hipStream_t s);
+// The same over nb dense n x n parents: parent y is A + y*xs (and B + y*xs),
+// its 7^L blocks start at S + y*os (T + y*os); the combine writes parent y
+// at C + y*cs with leading dimension ldc from M + y*ms.
+hipError_t launch_strassen_preadd_batch(int levels, int64_t n, int nb, const float* A, const float* B,
+                                        float* S, float* T, int64_t xs, int64_t os, hipStream_t s);
+hipError_t launch_strassen_combine_batch(int levels, int64_t n, int nb, const float* M, float* C,
+                                         int64_t ldc, int64_t ms, int64_t cs, hipStream_t s);
 
 }  // namespace paco

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <array>
 #include <cstring>
 
 #include "../../include/paco.h"
@@ -163,6 +164,273 @@ extern "C" paco_status paco_strassen_mm(paco_ctx ctx, int64_t n, const float* A,
   {
     TimeScope ts(ctx, 2);
     e = launch_strassen_combine(levels, n, M, C, ctx->stream);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "Strassen combine");
+  return PACO_OK;
+}
+
+// ------------------------------------------------------------------------
+// Pruned-BFS PACO Strassen (paco_strassen_pbfs).
+
+#include <cmath>
+
+#include "strassen_sched.h"
+
+namespace {
+
+// Plan of one (n, p, gamma, base, precision): the schedule, where each
+// depth's S, T and M live in the Strassen workspace, and the leaf launch.
+struct SPlan : paco::DevPlan {
+  paco::SSchedule sched;
+  int fused = 0;                      // depths 1..fused come from one fused pre-add
+  int first = 0;                      // first depth that hands out nodes
+  std::vector<int64_t> s_off, t_off, m_off;   // per depth, in floats (depth >= fused)
+  int64_t total = 0;                  // floats of S, T, M
+  std::vector<std::array<int64_t, 4>> prob;   // (depth, node, h, unused) per leaf problem
+  paco::Problem* d_probs = nullptr;
+  const void* probs_base = nullptr;   // workspace address d_probs points into
+  int prec = 0;
+  ~SPlan() override {
+    if (d_probs) (void)hipFree(d_probs);
+  }
+};
+
+paco_status strassen_args(paco_ctx ctx, const paco_strassen_desc* d, int* p, int64_t* base) {
+  if (!d || d->n < 0 || d->gamma < 0 || d->base < 0 || d->p < 0 || d->leaf < PACO_PREC_FP32 ||
+      d->leaf > PACO_PREC_AUTO) {
+    set_err(ctx, "invalid Strassen descriptor");
+    return PACO_ERR_INVALID_ARG;
+  }
+  if (d->n >= (1ll << 31)) {
+    set_err(ctx, "Strassen dimension too large");
+    return PACO_ERR_UNSUPPORTED;
+  }
+  *p = d->p > 0 ? d->p : std::max(1, ctx->num_cus / 32);
+  if (*p > ctx->num_cus) {
+    set_err(ctx, "Strassen processors exceed the compute units");
+    return PACO_ERR_INVALID_ARG;
+  }
+  *base = d->base > 0 ? d->base : 256;
+  return PACO_OK;
+}
+
+}  // namespace
+
+extern "C" paco_status paco_strassen_schedule(int64_t n, int32_t p, int32_t gamma, int64_t base,
+                                              paco_strassen_level* levels, int32_t cap, int32_t* n_levels,
+                                              double* work_classic, double* work_strassen) {
+  if (n < 1 || n >= (1ll << 31) || p < 1 || p > 65536 || gamma < 0 || base < 1 || !n_levels || cap < 0 ||
+      (cap > 0 && !levels))
+    return PACO_ERR_INVALID_ARG;
+  SSchedule s = strassen_schedule(n, p, gamma, base);
+  *n_levels = (int32_t)s.levels.size();
+  for (int32_t i = 0; i < cap && i < (int32_t)s.levels.size(); ++i) {
+    const SLevel& lv = s.levels[i];
+    levels[i].depth = lv.depth;
+    levels[i].super_round = lv.super_round ? 1 : 0;
+    levels[i].h = lv.h;
+    levels[i].nodes = lv.nodes;
+    levels[i].assigned = lv.assigned;
+  }
+  const double omega = std::log2(7.0);
+  for (int j = 0; j < p; ++j) {
+    double wc = 0, ws = 0;
+    for (const auto& dn : s.per_proc[j]) {
+      const double h = (double)s.levels[dn.first].h;
+      wc += h * h * h;
+      ws += std::pow(h, omega);
+    }
+    if (work_classic) work_classic[j] = wc;
+    if (work_strassen) work_strassen[j] = ws;
+  }
+  return PACO_OK;
+}
+
+extern "C" paco_status paco_strassen_pbfs(paco_ctx ctx, const paco_strassen_desc* d, paco_strassen_result* out) {
+  if (!ctx) return PACO_ERR_INVALID_ARG;
+  int p;
+  int64_t base;
+  paco_status st = strassen_args(ctx, d, &p, &base);
+  if (st != PACO_OK) return st;
+  const int64_t n = d->n;
+  if (n == 0) return PACO_OK;
+  if (!d->A || !d->B || !d->C) {
+    set_err(ctx, "null operand");
+    return PACO_ERR_INVALID_ARG;
+  }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+
+  // ---- plan
+  SSchedule sched = strassen_schedule(n, p, d->gamma, base);
+  int first = 0;
+  while (sched.levels[first].assigned == 0) ++first;
+  const int prec = d->leaf == PACO_PREC_AUTO ? (sched.levels[first].h >= 1024 ? PREC_BF16X3 : PREC_BF16X6)
+                                              : (int)d->leaf;
+  if (out) {
+    memset(out, 0, sizeof *out);
+    out->p = p;
+    out->super_rounds = sched.super_rounds;
+    out->max_depth = sched.levels.back().depth;
+    out->leaf = (paco_precision)prec;
+    double mx = 0, mn = 1e300;
+    for (int j = 0; j < p; ++j) {
+      double w = 0;
+      for (const auto& dn : sched.per_proc[j]) {
+        const double h = (double)sched.levels[dn.first].h;
+        w += h * h * h;
+        out->nodes += 1;
+      }
+      mx = std::max(mx, w);
+      mn = std::min(mn, w);
+    }
+    out->max_work = mx;
+    out->min_work = mn;
+  }
+  if (first == 0) {   // the root itself is handed out: one classic product on all compute units
+    paco_mm_desc md;
+    memset(&md, 0, sizeof md);
+    md.n = md.m = md.k = n;
+    md.sr = PACO_SR_PLUS_TIMES_F32;
+    md.A = d->A; md.B = d->B; md.C = d->C;
+    md.precision = (paco_precision)prec;
+    md.part = PACO_PART_PACO;
+    return paco_semiring_mm_ex(ctx, &md, nullptr);
+  }
+
+  char key[200];
+  snprintf(key, sizeof key, "spbfs/%lld/%d/%d/%lld/%d", (long long)n, p, d->gamma, (long long)base, prec);
+  SPlan* sp = nullptr;
+  auto itp = ctx->plans.find(key);
+  if (itp != ctx->plans.end()) {
+    sp = static_cast<SPlan*>(itp->second.get());
+  } else {
+    std::unique_ptr<SPlan> np(new SPlan());
+    np->sched = sched;
+    np->first = first;
+    np->fused = std::min(first, 3);
+    np->prec = prec;
+    const int nd = (int)sched.levels.size();
+    np->s_off.assign(nd, -1);
+    np->t_off.assign(nd, -1);
+    np->m_off.assign(nd, -1);
+    int64_t off = 0;
+    for (int dd = np->fused; dd < nd; ++dd) {
+      const int64_t blk = sched.levels[dd].nodes * sched.levels[dd].h * sched.levels[dd].h;
+      np->s_off[dd] = off; off += blk;
+      np->t_off[dd] = off; off += blk;
+      np->m_off[dd] = off; off += blk;
+    }
+    np->total = off;
+    // leaf problems: processor group g = compute units [g C / p, (g+1) C / p)
+    // runs its nodes in depth order, each split over the group by MM-1-Piece
+    const int C = ctx->num_cus;
+    std::vector<TaggedPiece> tp;
+    std::vector<Piece> local;
+    std::vector<ProbGeom> geom;
+    for (int g = 0; g < p; ++g) {
+      const int c0 = (int)((int64_t)g * C / p), c1 = (int)((int64_t)(g + 1) * C / p);
+      for (const auto& dn : sched.per_proc[g]) {
+        const int64_t h = sched.levels[dn.first].h;
+        const int32_t pi = (int32_t)np->prob.size();
+        np->prob.push_back({dn.first, dn.second, h, 0});
+        geom.push_back(ProbGeom{h, h, h});
+        PartOpts po;
+        po.p = c1 - c0;
+        po.q[0] = 16; po.q[1] = 16; po.q[2] = 32;
+        po.kcut_cost = default_kcut_cost(PACO_SR_PLUS_TIMES_F32);
+        for (const Piece& pc : partition_mm1(h, h, h, po)) {
+          if (pc.empty()) continue;
+          tp.push_back({pc, pi, c0 + pc.proc});
+          local.push_back(pc);
+        }
+      }
+    }
+    np->h = build_plan(tp, C, true, geom);
+    np->tile = choose_ring_tile(local, prec);
+    np->fam = 2;
+    np->p = p;
+    st = upload_plan(ctx, np.get());
+    if (st != PACO_OK) return st;
+    if ((e = hipMalloc(&np->d_probs, sizeof(Problem) * np->prob.size())) != hipSuccess)
+      return hip_fail(ctx, e, "Strassen problem table");
+    sp = np.get();
+    ctx->plans[key] = std::move(np);
+  }
+
+  // ---- workspace and the leaf problem table
+  st = ensure_sws(ctx, (uint64_t)sp->total * 4);
+  if (st != PACO_OK) return st;
+  st = ensure_ws(ctx, (uint64_t)sp->h.temp_elems * 4);
+  if (st != PACO_OK) return st;
+  float* W = (float*)ctx->sws;
+  if (sp->probs_base != ctx->sws) {
+    std::vector<Problem> probs(sp->prob.size());
+    for (size_t i = 0; i < probs.size(); ++i) {
+      const int dd = (int)sp->prob[i][0];
+      const int64_t j = sp->prob[i][1], h = sp->prob[i][2];
+      Problem& q = probs[i];
+      q.A = W + sp->s_off[dd] + j * h * h;
+      q.B = W + sp->t_off[dd] + j * h * h;
+      q.C = W + sp->m_off[dd] + j * h * h;
+      q.lda = q.ldb = q.ldc = h;
+      q.n = q.m = q.k = (int32_t)h;
+      q.accumulate = 0;
+    }
+    // the stream may still read the old table: wait before replacing it
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_fail(ctx, e, "Strassen table sync");
+    if ((e = hipMemcpy(sp->d_probs, probs.data(), sizeof(Problem) * probs.size(), hipMemcpyHostToDevice)) !=
+        hipSuccess)
+      return hip_fail(ctx, e, "Strassen table upload");
+    sp->probs_base = ctx->sws;
+  }
+  if (out) out->temp_bytes = (uint64_t)sp->total * 4;
+
+  const auto& lv = sp->sched.levels;
+  const int nd = (int)lv.size();
+  // ---- pre-additions, top down
+  {
+    TimeScope ts(ctx, 2);
+    e = launch_strassen_preadd(sp->fused, n, d->A, d->B, W + sp->s_off[sp->fused], W + sp->t_off[sp->fused],
+                               ctx->stream);
+    for (int dd = sp->fused + 1; dd < nd && e == hipSuccess; ++dd) {
+      const int64_t hp = lv[dd - 1].h, hc = lv[dd].h;
+      const int64_t a = lv[dd - 1].assigned, cnt = lv[dd - 1].nodes - a;
+      e = launch_strassen_preadd_batch(1, hp, (int)cnt, W + sp->s_off[dd - 1] + a * hp * hp,
+                                       W + sp->t_off[dd - 1] + a * hp * hp, W + sp->s_off[dd], W + sp->t_off[dd],
+                                       hp * hp, 7 * hc * hc, ctx->stream);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "Strassen pre-add");
+  // ---- every handed-out node, one persistent launch
+  ProbRef pr;
+  memset(&pr, 0, sizeof pr);
+  pr.table = sp->d_probs;
+  bool v4 = true;
+  for (const auto& q : sp->prob) v4 = v4 && q[2] % 4 == 0;
+  pr.vec_ok = v4 ? 1 : 0;
+  {
+    TimeScope ts(ctx, 0);
+    e = launch_ring(sp->prec, sp->tile, pr, sp->d_items, sp->d_wg_off, sp->h.nwg, sp->h.xcd_remap, ctx->ws,
+                    ctx->stream);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "Strassen node launch");
+  if (!sp->h.tiles.empty()) {
+    TimeScope ts(ctx, 1);
+    e = launch_reduce(SR_RING, pr, sp->d_tiles, (int)sp->h.tiles.size(), sp->d_srcs, ctx->ws, ctx->stream,
+                      sp->h.red_vec);
+    if (e != hipSuccess) return hip_fail(ctx, e, "Strassen node reduce");
+  }
+  // ---- combines, bottom up
+  {
+    TimeScope ts(ctx, 2);
+    for (int dd = nd - 1; dd > sp->fused && e == hipSuccess; --dd) {
+      const int64_t hp = lv[dd - 1].h, hc = lv[dd].h;
+      const int64_t a = lv[dd - 1].assigned, cnt = lv[dd - 1].nodes - a;
+      e = launch_strassen_combine_batch(1, hp, (int)cnt, W + sp->m_off[dd], W + sp->m_off[dd - 1] + a * hp * hp,
+                                        hp, 7 * hc * hc, hp * hp, ctx->stream);
+    }
+    if (e == hipSuccess) e = launch_strassen_combine(sp->fused, n, W + sp->m_off[sp->fused], d->C, ctx->stream);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "Strassen combine");
   return PACO_OK;

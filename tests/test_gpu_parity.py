@@ -126,3 +126,44 @@ def test_strassen_small_integers_exact(ctx, levels):
     C = host(ctx.strassen_mm(dev(A), dev(B), levels=levels, leaf="bf16x3"))
     expect = oracle.strassen_i64(A.astype(np.int64), B.astype(np.int64), levels)
     assert np.array_equal(C.astype(np.int64), expect)
+
+
+# ------------------------------------------------- pruned-BFS PACO Strassen
+
+@pytest.mark.parametrize("n,p,gamma,base", [(512, 8, 0, 64), (512, 256, 0, 32), (384, 3, 0, 16),
+                                            (500, 5, 0, 8), (256, 1, 0, 64), (512, 7, 1, 32),
+                                            (448, 64, 2, 16)])
+def test_strassen_pbfs_small_integers_exact(ctx, n, p, gamma, base):
+    # Strassen is exact over the integers; with entries in {-2..2} every
+    # S, T, M and C value is an integer below 2^24, so any depth of the
+    # pruned-BFS schedule must reproduce the classic product bit for bit
+    print(f"case: strassen pbfs small-int n={n} p={p} gamma={gamma} base={base}", flush=True)
+    A, B = workloads.small_int_operands(n, n, n, seed=11)
+    C, res = ctx.strassen_pbfs(dev(A), dev(B), p=p, gamma=gamma, base=base, leaf="bf16x3",
+                               return_result=True)
+    expect = oracle.ring_i64(A.astype(np.int64), B.astype(np.int64))
+    assert np.array_equal(host(C).astype(np.int64), expect)
+    levels, wc, _ = P.strassen_schedule(n, p, gamma, base)
+    assert res["nodes"] == sum(lv["assigned"] for lv in levels) and res["p"] == p
+    assert res["max_work"] == pytest.approx(wc.max()) and res["min_work"] == pytest.approx(wc.min())
+
+
+@pytest.mark.parametrize("p", [8, 256])
+def test_strassen_pbfs_float_normwise(ctx, p):
+    # float32 inputs U[-1,1], bf16x3 nodes: normwise error against the
+    # float64 classic product within the 2^-16 bound
+    print(f"case: strassen pbfs float n=1024 p={p}", flush=True)
+    A, B = workloads.strassen_operands(1024, seed=2)
+    C = host(ctx.strassen_pbfs(dev(A), dev(B), p=p, base=64, leaf="bf16x3"))
+    C64 = oracle.ring_f64(A, B)
+    err = np.linalg.norm(C.astype(np.float64) - C64) / (np.linalg.norm(A.astype(np.float64)) *
+                                                        np.linalg.norm(B.astype(np.float64)))
+    assert err <= 2.0 ** -16, err
+
+
+def test_strassen_pbfs_rejects_bad_arguments(ctx):
+    A = torch.zeros((64, 64), device=DEV)
+    with pytest.raises(Exception):
+        ctx.strassen_pbfs(A, A, p=100000)
+    with pytest.raises(Exception):
+        ctx.strassen_pbfs(A, A, gamma=-1)
