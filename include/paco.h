@@ -92,7 +92,14 @@ typedef enum paco_precision {
  *  GRID : the baseline the paper's experiments compare against in spirit:
  *         the same microkernel on a plain grid of output tiles with a
  *         split-k factor chosen by the autotuner. */
-typedef enum paco_part_mode { PACO_PART_PACO = 0, PACO_PART_GRID = 1 } paco_part_mode;
+typedef enum paco_part_mode {
+  PACO_PART_PACO = 0,   /* MM-1-Piece: one piece per processor */
+  PACO_PART_GRID = 1,   /* plain output-tile grid with split-k (baseline) */
+  PACO_PART_MULTI = 2   /* multi-piece pruned BFS (theorem mm): every cut
+                           halves a cuboid; a depth with >= p unassigned
+                           cuboids hands p of them out; at most 4 rounds,
+                           then the rest round-robin */
+} paco_part_mode;
 
 typedef struct paco_ctx_s* paco_ctx;
 
@@ -282,6 +289,9 @@ typedef struct paco_part_opts {
                                 summed throughput (heterogeneous variant) */
   int32_t multi_piece;       /* 1: PACO MM pruned-BFS multi-piece mode */
   double kcut_cost;          /* see paco_mm_desc (0 = 1, the paper's rule) */
+  int32_t max_rounds;        /* multi-piece: after this many rounds of p
+                                pieces hand out the rest round-robin
+                                (0 = divide down to the quanta) */
 } paco_part_opts;
 
 /* Host-only.  Partition the n-by-m-by-k cuboid over opts->p processors.

@@ -23,7 +23,7 @@ NEG_INF = -(1 << 30)
 SEMIRING = {"ring": 0, "plus_times": 0, "minplus": 1, "maxplus": 2, "bool": 3}
 PRECISION = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "auto": 3}
 PRECISION_NAME = {v: k for k, v in PRECISION.items()}
-PART = {"paco": 0, "grid": 1}
+PART = {"paco": 0, "grid": 1, "multi": 2}
 _DTYPE = {0: torch.float32, 1: torch.int32, 2: torch.int32, 3: torch.int32}
 
 
@@ -91,7 +91,8 @@ class PlanInfo(ctypes.Structure):
 class PartOpts(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("q_n", ctypes.c_int32), ("q_m", ctypes.c_int32),
                 ("q_k", ctypes.c_int32), ("weights", ctypes.POINTER(ctypes.c_double)),
-                ("multi_piece", ctypes.c_int32), ("kcut_cost", ctypes.c_double)]
+                ("multi_piece", ctypes.c_int32), ("kcut_cost", ctypes.c_double),
+                ("max_rounds", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -205,11 +206,11 @@ def strassen_schedule(n, p, gamma=0, base=256):
     return levels, wc, wsr
 
 
-def partition(n, m, k, p, q=(1, 1, 1), weights=None, multi_piece=False, kcut_cost=1.0):
+def partition(n, m, k, p, q=(1, 1, 1), weights=None, multi_piece=False, kcut_cost=1.0, max_rounds=0):
     """Host-only PACO partition (MM-1-Piece, or pruned-BFS multi-piece):
     a list of dicts with n0,n1,m0,m1,k0,k1, proc, temp, round, depth."""
     L = lib()
-    o = PartOpts(p, q[0], q[1], q[2], None, 1 if multi_piece else 0, kcut_cost)
+    o = PartOpts(p, q[0], q[1], q[2], None, 1 if multi_piece else 0, kcut_cost, max_rounds)
     if weights is not None:
         arr = (ctypes.c_double * p)(*[float(w) for w in weights])
         o.weights = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))

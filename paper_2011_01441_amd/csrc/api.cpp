@@ -238,7 +238,8 @@ extern "C" paco_status paco_partition(int64_t n, int64_t m, int64_t k, const pac
   po.q[2] = o->q_k > 0 ? o->q_k : 1;
   po.weights = o->weights;
   po.kcut_cost = o->kcut_cost > 0 ? o->kcut_cost : 1.0;
-  if (!(po.kcut_cost >= 1.0) || !std::isfinite(po.kcut_cost)) return PACO_ERR_INVALID_ARG;
+  if (!(po.kcut_cost >= 1.0) || !std::isfinite(po.kcut_cost) || o->max_rounds < 0) return PACO_ERR_INVALID_ARG;
+  po.max_rounds = o->max_rounds;
   if (o->weights)
     for (int i = 0; i < o->p; ++i)
       if (!(o->weights[i] > 0) || !std::isfinite(o->weights[i])) return PACO_ERR_INVALID_ARG;
@@ -334,14 +335,15 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
   std::vector<Piece> pcs;
   int tile = 0, tm = 0, tn = 0, bk = 32;
   double kcut_cost_used = 0.0;
-  if (part == PACO_PART_PACO) {
+  if (part != PACO_PART_GRID) {
     PartOpts po;
     po.kcut_cost = kcut_cost;
+    po.max_rounds = 4;
     if (fam == 1) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
     else if (fam == 2) { po.q[0] = 16; po.q[1] = 16; po.q[2] = 32; }
     auto part_for = [&](int pp) {
       po.p = pp;
-      std::vector<Piece> v = partition_mm1(n, m, k, po);
+      std::vector<Piece> v = part == PACO_PART_MULTI ? partition_multi(n, m, k, po) : partition_mm1(n, m, k, po);
       if (fam == 1)  // bits -> words in m
         for (Piece& pc : v) { pc.m0 /= 32; pc.m1 = words(pc.m1); }
       return v;
@@ -393,12 +395,14 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
             if (f > 1 && work < (double)pt * 4 * tile_work) continue;
             if (pt > 65536) continue;
             std::vector<Piece> v = part_for(pt);
+            std::vector<double> load(pt, 0.0);   // per processor (multi-piece: several pieces)
             double worst = 0, temps = 0;
             for (const Piece& pc : v) {
               if (pc.empty()) continue;
               const double tl =
                   (double)((pc.n1 - pc.n0 + tm_ - 1) / tm_) * (double)((pc.m1 - pc.m0 + tn_ - 1) / tn_);
-              worst = std::max(worst, tl * tm_ * tn_ * ((double)(pc.k1 - pc.k0) + k_ovh));
+              load[pc.proc] += tl * tm_ * tn_ * ((double)(pc.k1 - pc.k0) + k_ovh);
+              worst = std::max(worst, load[pc.proc]);
               if (pc.k0 > 0) temps += (double)(pc.n1 - pc.n0) * (double)(pc.m1 - pc.m0);  // upper k-part
             }
             const double rounds = (double)pt / slots;
@@ -453,10 +457,10 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
       for (Piece& pc : pcs) { pc.m0 /= 32; pc.m1 = words(pc.m1); }
   }
   std::vector<TaggedPiece> tp(pcs.size());
-  for (size_t i = 0; i < pcs.size(); ++i) tp[i] = {pcs[i], 0, part == PACO_PART_PACO ? pcs[i].proc : (int)i};
-  const int nwg = part == PACO_PART_PACO ? p : (int)pcs.size();
+  for (size_t i = 0; i < pcs.size(); ++i) tp[i] = {pcs[i], 0, part != PACO_PART_GRID ? pcs[i].proc : (int)i};
+  const int nwg = part != PACO_PART_GRID ? p : (int)pcs.size();
   std::vector<ProbGeom> geom{{n, mu, ku}};
-  np->h = build_plan(tp, nwg, part == PACO_PART_PACO, geom);
+  np->h = build_plan(tp, nwg, part != PACO_PART_GRID, geom);
   np->tile = tile;
   np->fam = fam;
   np->p = p;
@@ -470,8 +474,8 @@ extern "C" paco_status paco_plan_export(int64_t n, int64_t m, int64_t k, paco_se
                                         paco_plan_info* info, int64_t* items, int32_t* wg_off, int32_t* tiles,
                                         int64_t* srcs) {
   if (!info || n <= 0 || m <= 0 || k <= 0 || n >= (1ll << 31) || m >= (1ll << 31) || k >= (1ll << 31) ||
-      sr < PACO_SR_PLUS_TIMES_F32 || sr > PACO_SR_OR_AND_B1 || part < PACO_PART_PACO || part > PACO_PART_GRID ||
-      p < 0 || (p == 0 && part != PACO_PART_PACO) || p > 65536 || split_k < 0 || num_cus < 1 ||
+      sr < PACO_SR_PLUS_TIMES_F32 || sr > PACO_SR_OR_AND_B1 || part < PACO_PART_PACO || part > PACO_PART_MULTI ||
+      p < 0 || (p == 0 && part == PACO_PART_GRID) || p > 65536 || split_k < 0 || num_cus < 1 ||
       prec < PACO_PREC_FP32 || prec > PACO_PREC_AUTO)
     return PACO_ERR_INVALID_ARG;
   int pr = -1;
@@ -554,7 +558,7 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
     return PACO_ERR_INVALID_ARG;
   }
   if (d->precision < PACO_PREC_FP32 || d->precision > PACO_PREC_AUTO || d->part < PACO_PART_PACO ||
-      d->part > PACO_PART_GRID || d->p < 0 || d->grid_split_k < 0 || d->verify_rows < 0 ||
+      d->part > PACO_PART_MULTI || d->p < 0 || d->grid_split_k < 0 || d->verify_rows < 0 ||
       !(d->kcut_cost == 0 || (d->kcut_cost >= 1 && std::isfinite(d->kcut_cost)))) {
     set_err(ctx, "invalid option");
     return PACO_ERR_INVALID_ARG;
@@ -598,7 +602,7 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
     if (d->precision == PACO_PREC_AUTO) z.prec = auto_precision(z.k);
     else z.prec = (int)d->precision;
   }
-  const int p = d->p > 0 ? d->p : (d->part == PACO_PART_PACO ? 0 : ctx->num_cus);
+  const int p = d->p > 0 ? d->p : (d->part != PACO_PART_GRID ? 0 : ctx->num_cus);
   if (p > 65536) {
     set_err(ctx, "p above 65536");
     return PACO_ERR_INVALID_ARG;
@@ -660,7 +664,7 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   }
   if (res) {
     res->precision = (paco_precision)(z.prec < 0 ? PACO_PREC_FP32 : z.prec);
-    res->p = d->part == PACO_PART_PACO ? dp->p : dp->h.nwg;
+    res->p = d->part != PACO_PART_GRID ? dp->p : dp->h.nwg;
     res->n_pieces = dp->h.n_pieces;
     res->max_piece_volume = dp->h.vmax;
     res->min_piece_volume = dp->h.vmin;

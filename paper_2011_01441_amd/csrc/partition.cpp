@@ -114,6 +114,11 @@ std::vector<Piece> partition_multi(int64_t n, int64_t m, int64_t k, const PartOp
       level.erase(level.begin(), level.begin() + o.p);
       ++round;
       if (level.empty()) break;
+      if (o.max_rounds > 0 && round >= o.max_rounds) {   // the rest round-robin
+        for (size_t j = 0; j < level.size(); ++j)
+          out.push_back(make_piece(level[j].b, (int)(j % o.p), round, level[j].depth));
+        break;
+      }
     }
     bool any_cuttable = false;
     for (const Node& nd : level)

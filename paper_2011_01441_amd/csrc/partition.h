@@ -21,6 +21,9 @@ struct PartOpts {
   // paper's rule; larger values prefer n and m cuts, which need no
   // temporary face)
   double kcut_cost = 1.0;
+  // multi-piece: rounds of p pieces before the rest goes out round-robin
+  // (0 = none; division then stops at the quanta)
+  int max_rounds = 0;
 };
 
 // MM-1-Piece (corollary mm-1-piece): exactly p pieces, piece j on proc j.

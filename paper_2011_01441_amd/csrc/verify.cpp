@@ -98,11 +98,17 @@ int choose_tile(const std::vector<Piece>& pcs, const int* cand, const double* ef
   for (int c = 0; c < nc; ++c) {
     int tm, tn;
     shape(cand[c], tm, tn);
+    // padded work of the busiest processor (a processor may hold several
+    // pieces in multi-piece mode)
+    int np = 0;
+    for (const Piece& p : pcs) np = std::max(np, p.proc + 1);
+    std::vector<double> load(np, 0.0);
     double worst = 0;
     for (const Piece& p : pcs) {
       if (p.empty()) continue;
       double tiles = (double)((p.n1 - p.n0 + tm - 1) / tm) * (double)((p.m1 - p.m0 + tn - 1) / tn);
-      worst = std::max(worst, tiles * tm * tn * (double)(p.k1 - p.k0) * eff[c]);
+      load[p.proc] += tiles * tm * tn * (double)(p.k1 - p.k0) * eff[c];
+      worst = std::max(worst, load[p.proc]);
     }
     if (worst < bestc) {
       bestc = worst;

@@ -167,3 +167,33 @@ def test_strassen_pbfs_rejects_bad_arguments(ctx):
         ctx.strassen_pbfs(A, A, p=100000)
     with pytest.raises(Exception):
         ctx.strassen_pbfs(A, A, gamma=-1)
+
+
+# --------------------------------------------- multi-piece pruned BFS (GPU)
+
+@pytest.mark.parametrize("p", [0, 3, 251, 256])
+def test_minplus_multi_piece_bit_exact(ctx, p):
+    print(f"case: minplus multi-piece p={p}", flush=True)
+    A, B = workloads.minplus_operands(384, 256, 320, seed=12)
+    C, res = ctx.semiring_mm(dev(A), dev(B), "minplus", part="multi", p=p, return_result=True)
+    assert np.array_equal(host(C), oracle.minplus(A, B))
+    assert res["n_pieces"] >= res["p"]
+
+
+def test_ring_multi_piece_small_integers_exact(ctx):
+    print("case: ring multi-piece small ints p=97", flush=True)
+    A, B = workloads.small_int_operands(700, 530, 1500, seed=13)
+    C = host(ctx.semiring_mm(dev(A), dev(B), "ring", part="multi", p=97, precision="bf16x3"))
+    assert np.array_equal(C.astype(np.int64), A.astype(np.int64) @ B.astype(np.int64))
+
+
+def test_bool_and_maxplus_multi_piece(ctx):
+    print("case: bool and maxplus multi-piece", flush=True)
+    n, m, k = 300, 333, 1000
+    _, _, ap, bp = workloads.bool_operands(n, m, k, density=0.01, seed=14)
+    C = host(ctx.semiring_mm(dev(ap.view(np.int32)), dev(bp.view(np.int32)), "bool", n=n, m=m, k=k,
+                             part="multi", p=200))
+    assert np.array_equal(C.view(np.uint32), oracle.bool_packed(ap, bp, n, m, k))
+    A, B = workloads.maxplus_operands(257, 129, 513, seed=15)
+    C = host(ctx.semiring_mm(dev(A), dev(B), "maxplus", part="multi", p=3))
+    assert np.array_equal(C, oracle.maxplus(A, B))

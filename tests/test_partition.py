@@ -143,3 +143,20 @@ def test_kcut_cost_option():
 def test_temp_flags_follow_k0():
     for pc in P.partition(64, 64, 4096, 64):
         assert pc["temp"] == (1 if pc["k0"] > 0 else 0)
+
+
+@pytest.mark.parametrize("p,rounds", [(3, 1), (3, 2), (200, 2), (251, 4), (256, 1)])
+def test_multi_piece_round_cap(p, rounds):
+    """max_rounds: rounds of exactly p pieces, then every remaining cuboid
+    round-robin; the pieces still tile the cuboid."""
+    n, m, k = 512, 384, 640
+    pcs = P.partition(n, m, k, p, multi_piece=True, max_rounds=rounds)
+    vol = sum((q["n1"] - q["n0"]) * (q["m1"] - q["m0"]) * (q["k1"] - q["k0"]) for q in pcs)
+    assert vol == n * m * k
+    by_round = {}
+    for q in pcs:
+        by_round.setdefault(q["round"], []).append(q)
+    full = sorted(r for r in by_round if r < rounds)
+    for r in full:
+        assert len(by_round[r]) == p and sorted(q["proc"] for q in by_round[r]) == list(range(p))
+    assert max(by_round) <= rounds

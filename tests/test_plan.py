@@ -125,3 +125,20 @@ def test_default_choice_plan_replay(sr, n, m, k):
     C, info = replay(sr, A, B, n, m, k, part="paco", p=0)
     np.testing.assert_array_equal(C, ref)
     assert info["n_wg"] % 256 == 0   # slots (or 4x slots) of 256 compute units
+
+
+@pytest.mark.parametrize("p", [3, 200, 251, 256])
+def test_multi_piece_plan_replay(p):
+    """Multi-piece pruned BFS (part="multi"): several pieces per processor,
+    each (i, j, l) still covered once and the result the oracle's."""
+    A, B = workloads.minplus_operands(384, 256, 320, seed=7)
+    C, info = replay("minplus", A, B, 384, 256, 320, part="multi", p=p)
+    np.testing.assert_array_equal(C, oracle.minplus(A, B))
+    items, wg, _, _, _ = P.plan_export(384, 256, 320, "minplus", part="multi", p=p)
+    assert info["n_wg"] == p and len(items) >= p
+
+
+def test_multi_piece_ring_plan_replay():
+    A, B = workloads.small_int_operands(300, 200, 700, seed=4)
+    C, _ = replay("ring", A.astype(np.int64), B.astype(np.int64), 300, 200, 700, part="multi", p=97)
+    np.testing.assert_array_equal(C, A.astype(np.int64) @ B.astype(np.int64))
