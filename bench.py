@@ -274,6 +274,8 @@ def main():
     ap.add_argument("--verify-rows", type=int, default=64)
     ap.add_argument("--no-server", action="store_true", help="skip the request-server runs")
     ap.add_argument("--server-requests", type=int, default=4096)
+    ap.add_argument("--no-calibrate", action="store_true",
+                    help="ring workloads: skip the measured processor throughputs (equal weights)")
     ap.add_argument("--hold", type=float, default=0.0,
                     help="after the JSON line, keep running the step for this many seconds "
                          "(for sampling clocks and power from outside)")
@@ -308,6 +310,13 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration sum {float(tot):.0f}")
         del src
+
+    # ---- measured processor throughputs for the heterogeneous split (ring)
+    rates = None
+    if w["kind"] == "ring" and not args.no_calibrate:
+        rates = ctx.calibrate()
+        ctx.set_processor_weights(rates)
+        log("processor rates per XCD (bf16 TFLOP/s per CU):", [round(float(x), 3) for x in rates[::32]])
 
     # ---- PACO path
     res = None
@@ -415,6 +424,8 @@ def main():
         "config": {"workload": args.workload, "desc": w["desc"], "precision": prec,
                    "partition": "PACO MM-1-Piece", "p": res["p"] if res else None,
                    "kcut_cost": res["kcut_cost"] if res else None,
+                   "processor_weights": ("measured per-XCD matrix-core rates, max/min %.4f" %
+                                         (rates.max() / rates.min())) if rates is not None else "equal",
                    "pieces": res["n_pieces"] if res else None,
                    "kcut_faces": res["n_kcuts"] if res else None,
                    "parallelism": "one GPU, 256 CUs"},

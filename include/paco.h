@@ -153,6 +153,13 @@ typedef struct paco_mm_desc {
                                    read back); 0 = library default: 16
                                    for the ring, chosen among 1, 4 and 16
                                    with the tile and p for the others */
+  const double* weights;        /* NULL, or p positive processor throughputs
+                                   (host memory, read during the call): PACO
+                                   mode with an explicit p cuts each cuboid
+                                   in the ratio of the summed throughputs of
+                                   the two halves of the processor list (the
+                                   heterogeneous variant of the experiments
+                                   section), e.g. from paco_calibrate */
 } paco_mm_desc;
 
 typedef struct paco_mm_result {
@@ -170,6 +177,21 @@ typedef struct paco_mm_result {
 /* Extended form: explicit leading dimensions, accumulation, precision,
  * partition mode and processor count.  `out` may be NULL. */
 paco_status paco_semiring_mm_ex(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* out);
+
+/* Measure the throughput of p processors (workgroups of one launch, p a
+ * multiple of 8, at most 8 x compute units) for the heterogeneous split
+ * (section "Extension to Heterogeneous Computing System"): all of them run
+ * the same matrix-core chain at once, after an untimed run of the same
+ * length so that clocks and power settle; each processor's rate is that of
+ * its XCD (processors q of XCD q / (p/8), as PACO launches place them),
+ * in bf16 TFLOP/s.  iters = 0: about 50 ms per run.  Synchronous. */
+paco_status paco_calibrate(paco_ctx ctx, int32_t p, int32_t iters, double* rates);
+
+/* Keep p processor throughputs in the context (copied): from then on ring
+ * calls in PACO mode that leave p and weights at 0 run on p processors with
+ * the heterogeneous split.  p = 0 or weights = NULL clears them.  p must be
+ * the compute-unit count (the ring kernel holds one workgroup per unit). */
+paco_status paco_set_processor_weights(paco_ctx ctx, int32_t p, const double* weights);
 
 /* ------------------------------------------------------------- Strassen */
 

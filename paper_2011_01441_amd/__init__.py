@@ -42,7 +42,8 @@ class MMDesc(ctypes.Structure):
                 ("accumulate", ctypes.c_int32), ("precision", ctypes.c_int),
                 ("part", ctypes.c_int), ("p", ctypes.c_int32),
                 ("grid_split_k", ctypes.c_int32), ("verify_rows", ctypes.c_int32),
-                ("verify_seed", ctypes.c_uint64), ("kcut_cost", ctypes.c_double)]
+                ("verify_seed", ctypes.c_uint64), ("kcut_cost", ctypes.c_double),
+                ("weights", ctypes.c_void_p)]
 
 
 class MMResult(ctypes.Structure):
@@ -150,6 +151,8 @@ def lib():
     L.paco_semiring_mm.argtypes = [vp, i64, i64, i64, ci, vp, vp, vp]
     L.paco_semiring_mm_ex.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(MMResult)]
     L.paco_strassen_mm.argtypes = [vp, i64, vp, vp, vp, ci, ci]
+    L.paco_calibrate.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp]
+    L.paco_set_processor_weights.argtypes = [vp, ctypes.c_int32, vp]
     L.paco_strassen_pbfs.argtypes = [vp, ctypes.POINTER(StrassenDesc), ctypes.POINTER(StrassenResult)]
     L.paco_strassen_schedule.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, i64,
                                          ctypes.POINTER(StrassenLevel), ctypes.c_int32,
@@ -284,7 +287,7 @@ class Context:
 
     def semiring_mm(self, A, B, semiring="ring", *, n=None, m=None, k=None, C=None,
                     accumulate=False, precision="auto", part="paco", p=0, split_k=0,
-                    verify_rows=0, verify_seed=0, kcut_cost=0.0, return_result=False):
+                    verify_rows=0, verify_seed=0, kcut_cost=0.0, weights=None, return_result=False):
         """C = A (x) B.  Boolean operands are bit-packed int32 words; pass
         their logical sizes n, m, k.  Returns C (and a result dict)."""
         sr = SEMIRING[semiring]
@@ -305,9 +308,16 @@ class Context:
             C = torch.empty((n, mw), dtype=dt, device=A.device)
         else:
             self._check_tensor(C, "C", dt)
+        w = None
+        if weights is not None:
+            import numpy as np
+            w = np.ascontiguousarray(weights, np.float64)
+            if w.shape != (p,):
+                raise ValueError("weights need one entry per processor (explicit p)")
         d = MMDesc(n, m, k, sr, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C), C.stride(0),
                    1 if accumulate else 0, PRECISION[precision], PART[part], p, split_k,
-                   verify_rows, verify_seed, kcut_cost)
+                   verify_rows, verify_seed, kcut_cost,
+                   ctypes.c_void_p(w.ctypes.data) if w is not None else None)
         r = MMResult()
         self._stream()
         _check(self._L.paco_semiring_mm_ex(self._h, ctypes.byref(d), ctypes.byref(r)), self._h)
@@ -329,6 +339,26 @@ class Context:
         _check(self._L.paco_strassen_mm(self._h, n, _ptr(A), _ptr(B), _ptr(C), levels,
                                         PRECISION[leaf]), self._h)
         return C
+
+    def calibrate(self, p=0, iters=0):
+        """Measured throughput (bf16 TFLOP/s) of each of p processors
+        (default: compute units), for semiring_mm(weights=...)."""
+        import numpy as np
+        p = p or self._L.paco_num_cus(self._h)
+        r = np.zeros(p, np.float64)
+        self._stream()
+        _check(self._L.paco_calibrate(self._h, p, iters, ctypes.c_void_p(r.ctypes.data)), self._h)
+        return r
+
+    def set_processor_weights(self, weights=None):
+        """Default-p ring calls in PACO mode use these throughputs (one per
+        compute unit); None clears them."""
+        import numpy as np
+        if weights is None:
+            _check(self._L.paco_set_processor_weights(self._h, 0, None), self._h)
+            return
+        w = np.ascontiguousarray(weights, np.float64)
+        _check(self._L.paco_set_processor_weights(self._h, len(w), ctypes.c_void_p(w.ctypes.data)), self._h)
 
     def strassen_pbfs(self, A, B, C=None, p=0, gamma=0, base=0, leaf="bf16x3", return_result=False):
         """PACO Strassen with the pruned-BFS schedule over p processor groups

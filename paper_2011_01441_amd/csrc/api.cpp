@@ -328,7 +328,7 @@ static int env_tile(const char* name, int count, int dflt) {
 
 // Host part of a semiring MM plan: partition, tile choice, work lists.
 void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
-                  int num_cus, DevPlan* np, double kcut_cost) {
+                  int num_cus, DevPlan* np, double kcut_cost, const double* weights) {
   const bool is_bool = sr == PACO_SR_OR_AND_B1;
   const int64_t mu = is_bool ? words(m) : m, ku = is_bool ? words(k) : k;
   const int fam = sr == PACO_SR_PLUS_TIMES_F32 ? 2 : (is_bool ? 1 : 0);
@@ -339,6 +339,7 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
     PartOpts po;
     po.kcut_cost = kcut_cost;
     po.max_rounds = 4;
+    po.weights = weights;   // explicit p only (checked by the caller)
     if (fam == 1) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
     else if (fam == 2) { po.q[0] = 16; po.q[1] = 16; po.q[2] = 32; }
     auto part_for = [&](int pp) {
@@ -602,7 +603,30 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
     if (d->precision == PACO_PREC_AUTO) z.prec = auto_precision(z.k);
     else z.prec = (int)d->precision;
   }
-  const int p = d->p > 0 ? d->p : (d->part != PACO_PART_GRID ? 0 : ctx->num_cus);
+  const double* weights = d->weights;
+  int p = d->p > 0 ? d->p : (d->part != PACO_PART_GRID ? 0 : ctx->num_cus);
+  if (!weights && d->p == 0 && d->part == PACO_PART_PACO && d->sr == PACO_SR_PLUS_TIMES_F32 &&
+      (int)ctx->weights.size() == ctx->num_cus) {
+    weights = ctx->weights.data();   // the context's measured throughputs
+    p = ctx->num_cus;
+  }
+  uint64_t whash = 0;
+  if (weights) {
+    if (d->part != PACO_PART_PACO || p <= 0) {
+      set_err(ctx, "processor weights need PACO mode and an explicit p");
+      return PACO_ERR_INVALID_ARG;
+    }
+    whash = 1469598103934665603ull;   // FNV-1a over the weights' bytes, for the plan key
+    for (int i = 0; i < p; ++i) {
+      if (!(weights[i] > 0) || !std::isfinite(weights[i])) {
+        set_err(ctx, "processor weights must be positive and finite");
+        return PACO_ERR_INVALID_ARG;
+      }
+      unsigned char b[8];
+      memcpy(b, &weights[i], 8);
+      for (unsigned char c : b) whash = (whash ^ c) * 1099511628211ull;
+    }
+  }
   if (p > 65536) {
     set_err(ctx, "p above 65536");
     return PACO_ERR_INVALID_ARG;
@@ -614,8 +638,9 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   const double kc = d->kcut_cost > 0 ? d->kcut_cost : plan_kcut_cost((int)d->sr);
   const char* tenv = getenv(is_bool ? "PACO_BOOL_TILE" : (d->sr == PACO_SR_PLUS_TIMES_F32 ? "PACO_RING_TILE"
                                                                                            : "PACO_INT_TILE"));
-  snprintf(key, sizeof key, "mm/%d/%lld/%lld/%lld/%d/%d/%d/%d/%g/%.8s", (int)d->sr, (long long)z.n,
-           (long long)z.m, (long long)z.k, (int)d->part, p, d->grid_split_k, z.prec, kc, tenv ? tenv : "");
+  snprintf(key, sizeof key, "mm/%d/%lld/%lld/%lld/%d/%d/%d/%d/%g/%.8s/%llx", (int)d->sr, (long long)z.n,
+           (long long)z.m, (long long)z.k, (int)d->part, p, d->grid_split_k, z.prec, kc, tenv ? tenv : "",
+           (unsigned long long)whash);
   DevPlan* dp = nullptr;
   auto itp = ctx->plans.find(key);
   if (itp != ctx->plans.end()) {
@@ -623,7 +648,7 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   } else {
     std::unique_ptr<DevPlan> np(new DevPlan());
     make_mm_plan((int)d->sr, z.n, z.m, z.k, (int)d->part, p, d->grid_split_k, z.prec, ctx->num_cus,
-                 np.get(), kc);
+                 np.get(), kc, weights);
     paco_status st = upload_plan(ctx, np.get());
     if (st != PACO_OK) return st;
     dp = np.get();

@@ -33,6 +33,7 @@ struct paco_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
   int num_cus = 0;
+  std::vector<double> weights;   // processor throughputs for default-p ring calls (paco_set_processor_weights)
   uint64_t budget = 0;
   void* ws = nullptr;        // temporary faces
   uint64_t ws_bytes = 0;
@@ -70,7 +71,7 @@ int64_t words(int64_t bits);
 int auto_precision(int64_t k);
 bool ring_vec_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t m, int64_t k);
 void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
-                  int num_cus, DevPlan* np, double kcut_cost);
+                  int num_cus, DevPlan* np, double kcut_cost, const double* weights = nullptr);
 double default_kcut_cost(int sr);
 double plan_kcut_cost(int sr);
 

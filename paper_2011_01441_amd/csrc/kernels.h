@@ -74,4 +74,10 @@ hipError_t launch_strassen_preadd_batch(int levels, int64_t n, int nb, const flo
 hipError_t launch_strassen_combine_batch(int levels, int64_t n, int nb, const float* M, float* C,
                                          int64_t ldc, int64_t ms, int64_t cs, hipStream_t s);
 
+// Calibration: nwg workgroups of 256 threads each run `iters` rounds of four
+// bf16 matrix-core products per wave; workgroup w writes its start and end
+// (100 MHz real-time counter) to stamps[2w], stamps[2w+1].  `sink` (256
+// floats) is never written in practice.
+hipError_t launch_calib(int nwg, int iters, uint64_t* stamps, float* sink, hipStream_t s);
+
 }  // namespace paco

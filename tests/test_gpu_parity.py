@@ -197,3 +197,38 @@ def test_bool_and_maxplus_multi_piece(ctx):
     A, B = workloads.maxplus_operands(257, 129, 513, seed=15)
     C = host(ctx.semiring_mm(dev(A), dev(B), "maxplus", part="multi", p=3))
     assert np.array_equal(C, oracle.maxplus(A, B))
+
+
+# --------------------------------------- heterogeneous split (measured rates)
+
+def test_calibrate_rates(ctx):
+    print("case: calibrate 256 processors", flush=True)
+    r = ctx.calibrate(256, iters=20000)
+    assert r.shape == (256,) and np.all(np.isfinite(r)) and np.all(r > 0)
+    # one rate per XCD; together at most the dense bf16 peak
+    assert all(len(set(r[32 * x:32 * x + 32])) == 1 for x in range(8))
+    assert 0.2 * 2500 < r.sum() < 1.02 * 2500, r.sum()
+
+
+def test_weighted_split_exact(ctx):
+    print("case: weighted split minplus and ring", flush=True)
+    A, B = workloads.minplus_operands(384, 256, 320, seed=16)
+    w = 1.0 + (np.arange(256) % 4)            # four processor speeds
+    C, res = ctx.semiring_mm(dev(A), dev(B), "minplus", p=256, weights=w, return_result=True)
+    assert np.array_equal(host(C), oracle.minplus(A, B))
+    assert res["max_piece_volume"] > 2 * res["min_piece_volume"]   # faster processors got more
+    A, B = workloads.small_int_operands(1000, 700, 2048, seed=17)
+    C = host(ctx.semiring_mm(dev(A), dev(B), "ring", p=256, weights=w, precision="bf16x3"))
+    assert np.array_equal(C.astype(np.int64), A.astype(np.int64) @ B.astype(np.int64))
+    with pytest.raises(Exception):
+        ctx.semiring_mm(dev(A), dev(B), "ring", p=256, weights=-w)
+    with pytest.raises(Exception):
+        ctx.semiring_mm(dev(A), dev(B), "ring", weights=w)     # needs an explicit p
+    # weights held by the context serve default-p ring calls
+    ctx.set_processor_weights(w)
+    try:
+        C, res = ctx.semiring_mm(dev(A), dev(B), "ring", precision="bf16x3", return_result=True)
+        assert np.array_equal(host(C).astype(np.int64), A.astype(np.int64) @ B.astype(np.int64))
+        assert res["p"] == 256 and res["max_piece_volume"] > 2 * res["min_piece_volume"]
+    finally:
+        ctx.set_processor_weights(None)
