@@ -249,6 +249,52 @@ typedef struct paco_strassen_result {
 
 paco_status paco_strassen_pbfs(paco_ctx ctx, const paco_strassen_desc* d, paco_strassen_result* out);
 
+/* ------------------------------------------------------------- tuning */
+
+/* Measured choice for one shape.  `d` is a default PACO call (part PACO,
+ * p, kcut_cost, weights, verify_rows and accumulate all 0) on real
+ * operands; the tuner runs it and its alternatives -- ring: MM-1-Piece and
+ * multi-piece, k-cut cost 1/4/16/64, each ring tile; VALU semirings: each
+ * tile at CUs x its resident workgroups and 4 times that, k-cut cost
+ * 1/16/64 -- times each on the context stream (C is overwritten), and keeps
+ * the fastest in the context if it beats the default.  Later calls of the
+ * same (semiring, n, m, k, precision) with default options use it.
+ * Synchronous; candidates that fail (e.g. over the workspace budget) are
+ * skipped.  paco_tune_clear forgets every choice. */
+typedef struct paco_tune_result {
+  int32_t tuned;             /* 1: a candidate beat the default and was kept */
+  paco_part_mode part;
+  int32_t p, tile, weighted; /* tile: index of the kernel's tile list */
+  double kcut_cost;
+  double best_ms, default_ms;
+  int32_t candidates;        /* candidates timed */
+} paco_tune_result;
+
+paco_status paco_tune(paco_ctx ctx, const paco_mm_desc* d, paco_tune_result* out);
+paco_status paco_tune_clear(paco_ctx ctx);
+
+/* ------------------------------------------------------------ hipGraphs */
+
+/* A call captured once and replayed.  paco_graph_create runs the call
+ * eagerly on the context stream (building and uploading its plan, sizing
+ * the workspace), waits for it, then records the same call's kernel
+ * launches into a hipGraph on a private stream and instantiates it.
+ * paco_graph_launch replays those launches on `stream` (a hipStream_t as an
+ * opaque pointer; NULL = the context stream) with the operand pointers and
+ * sizes of the capture, reading whatever the buffers hold at replay time.
+ * The launches point into the context's workspace: a later call that
+ * grows it makes earlier graphs stale, and paco_graph_launch then returns
+ * PACO_ERR_INVALID_ARG instead of replaying (create graphs after the calls
+ * that need the most workspace, or use one context per graph).  The
+ * operand buffers must outlive the graph.  verify_rows must be 0.  Replays of one graph
+ * on one stream are ordered; replays that overlap with other calls on the
+ * same context race on its workspace. */
+typedef struct paco_graph_s* paco_graph;
+paco_status paco_graph_create(paco_ctx ctx, const paco_mm_desc* d, paco_graph* out);
+paco_status paco_graph_create_strassen(paco_ctx ctx, const paco_strassen_desc* d, paco_graph* out);
+paco_status paco_graph_launch(paco_graph g, void* stream);
+paco_status paco_graph_destroy(paco_graph g);
+
 /* Host-only: the schedule paco_strassen_pbfs runs.  levels[i] describes
  * depth i (the node dimension h, the nodes of the depth, how many were
  * handed out, whether the depth was a super-round); work_classic[j] and

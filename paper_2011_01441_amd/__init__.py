@@ -66,6 +66,13 @@ class StrassenResult(ctypes.Structure):
                 ("temp_bytes", ctypes.c_uint64), ("leaf", ctypes.c_int)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tuned", ctypes.c_int32), ("part", ctypes.c_int), ("p", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("weighted", ctypes.c_int32), ("kcut_cost", ctypes.c_double),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("candidates", ctypes.c_int32)]
+
+
 class StrassenLevel(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("super_round", ctypes.c_int32), ("h", ctypes.c_int64),
                 ("nodes", ctypes.c_int64), ("assigned", ctypes.c_int64)]
@@ -152,6 +159,12 @@ def lib():
     L.paco_semiring_mm_ex.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(MMResult)]
     L.paco_strassen_mm.argtypes = [vp, i64, vp, vp, vp, ci, ci]
     L.paco_calibrate.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp]
+    L.paco_tune.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(TuneResult)]
+    L.paco_tune_clear.argtypes = [vp]
+    L.paco_graph_create.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(vp)]
+    L.paco_graph_create_strassen.argtypes = [vp, ctypes.POINTER(StrassenDesc), ctypes.POINTER(vp)]
+    L.paco_graph_launch.argtypes = [vp, vp]
+    L.paco_graph_destroy.argtypes = [vp]
     L.paco_set_processor_weights.argtypes = [vp, ctypes.c_int32, vp]
     L.paco_strassen_pbfs.argtypes = [vp, ctypes.POINTER(StrassenDesc), ctypes.POINTER(StrassenResult)]
     L.paco_strassen_schedule.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, i64,
@@ -248,6 +261,29 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
 
 
+class Graph:
+    """A captured library call (paco_graph); launch() replays it on torch's
+    current stream.  Keeps its operand tensors alive."""
+
+    def __init__(self, ctx, h, keep):
+        self._ctx, self._h, self._keep = ctx, h, keep
+
+    def launch(self):
+        s = torch.cuda.current_stream(self._ctx.device).cuda_stream
+        _check(self._ctx._L.paco_graph_launch(self._h, ctypes.c_void_p(s)), self._ctx._h)
+
+    def close(self):
+        if self._h:
+            self._ctx._L.paco_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """A libpaco context on one device; launches on torch's current stream."""
 
@@ -284,6 +320,76 @@ class Context:
             raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
         if t.dim() != 2 or t.stride(1) != 1:
             raise ValueError(f"{name} must be 2-D with unit column stride")
+
+    def tune(self, A, B, semiring="ring", **kw):
+        """Time the default plan of this shape and its alternatives on these
+        operands (C is overwritten); keep the fastest for later default
+        calls.  Returns the tuner's result as a dict."""
+        if kw.get("C") is None:
+            raise ValueError("tuning needs the output buffer C")
+        d, keep = self._desc(A, B, semiring, **kw)
+        r = TuneResult()
+        self._stream()
+        _check(self._L.paco_tune(self._h, ctypes.byref(d), ctypes.byref(r)), self._h)
+        out = {f[0]: getattr(r, f[0]) for f in TuneResult._fields_}
+        out["part"] = {v: k for k, v in PART.items()}.get(out["part"], out["part"])
+        return out
+
+    def tune_clear(self):
+        _check(self._L.paco_tune_clear(self._h), self._h)
+
+    def graph(self, A, B, semiring="ring", **kw):
+        """Capture C = A (x) B (same arguments as semiring_mm, C required)
+        into a hipGraph; returns a Graph whose launch() replays it."""
+        if kw.get("C") is None:
+            raise ValueError("a captured call needs its output buffer C")
+        d, keep = self._desc(A, B, semiring, **kw)
+        self._stream()
+        h = ctypes.c_void_p()
+        _check(self._L.paco_graph_create(self._h, ctypes.byref(d), ctypes.byref(h)), self._h)
+        return Graph(self, h, (A, B, kw["C"], keep))
+
+    def graph_strassen(self, A, B, C, p=0, gamma=0, base=0, leaf="bf16x3"):
+        """Capture a pruned-BFS Strassen call into a hipGraph."""
+        for t, nm in ((A, "A"), (B, "B"), (C, "C")):
+            self._check_tensor(t, nm, torch.float32)
+        n = A.shape[0]
+        if A.shape != (n, n) or B.shape != (n, n) or C.shape != (n, n) or not all(
+                t.is_contiguous() for t in (A, B, C)):
+            raise ValueError("Strassen needs dense square operands of equal size")
+        d = StrassenDesc(n, _ptr(A), _ptr(B), _ptr(C), p, gamma, base, PRECISION[leaf])
+        self._stream()
+        h = ctypes.c_void_p()
+        _check(self._L.paco_graph_create_strassen(self._h, ctypes.byref(d), ctypes.byref(h)), self._h)
+        return Graph(self, h, (A, B, C))
+
+    def _desc(self, A, B, semiring="ring", *, n=None, m=None, k=None, C=None, accumulate=False,
+              precision="auto", part="paco", p=0, split_k=0, verify_rows=0, verify_seed=0, kcut_cost=0.0,
+              weights=None):
+        sr = SEMIRING[semiring]
+        dt = _DTYPE[sr]
+        self._check_tensor(A, "A", dt)
+        self._check_tensor(B, "B", dt)
+        if sr == 3:
+            if n is None or m is None or k is None:
+                raise ValueError("boolean operands need explicit n, m, k (bits)")
+        else:
+            n, k = A.shape
+            k2, m = B.shape
+            if k2 != k:
+                raise ValueError(f"inner sizes differ: {A.shape} x {B.shape}")
+        self._check_tensor(C, "C", dt)
+        w = None
+        if weights is not None:
+            import numpy as np
+            w = np.ascontiguousarray(weights, np.float64)
+            if w.shape != (p,):
+                raise ValueError("weights need one entry per processor (explicit p)")
+        d = MMDesc(n, m, k, sr, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(C), C.stride(0),
+                   1 if accumulate else 0, PRECISION[precision], PART[part], p, split_k,
+                   verify_rows, verify_seed, kcut_cost,
+                   ctypes.c_void_p(w.ctypes.data) if w is not None else None)
+        return d, w
 
     def semiring_mm(self, A, B, semiring="ring", *, n=None, m=None, k=None, C=None,
                     accumulate=False, precision="auto", part="paco", p=0, split_k=0,

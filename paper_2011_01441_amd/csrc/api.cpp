@@ -75,6 +75,7 @@ paco_status ensure_ws(paco_ctx ctx, uint64_t bytes) {
   // round up to 64 MiB so small growth steps do not reallocate every call
   uint64_t want = (bytes + (64ull << 20) - 1) & ~((64ull << 20) - 1);
   if (want > ctx->budget) want = bytes;
+  ctx->ws_gen += 1;
   if ((e = hipMalloc(&ctx->ws, want)) != hipSuccess) return hip_fail(ctx, e, "workspace alloc");
   ctx->ws_bytes = want;
   return PACO_OK;
@@ -328,7 +329,7 @@ static int env_tile(const char* name, int count, int dflt) {
 
 // Host part of a semiring MM plan: partition, tile choice, work lists.
 void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
-                  int num_cus, DevPlan* np, double kcut_cost, const double* weights) {
+                  int num_cus, DevPlan* np, double kcut_cost, const double* weights, int force_tile) {
   const bool is_bool = sr == PACO_SR_OR_AND_B1;
   const int64_t mu = is_bool ? words(m) : m, ku = is_bool ? words(k) : k;
   const int fam = sr == PACO_SR_PLUS_TIMES_F32 ? 2 : (is_bool ? 1 : 0);
@@ -376,7 +377,7 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
       const double k_ovh = fam == 0 ? 64.0 : 128.0;        // prologue + epilogue, in k units
       const double kcs[4] = {1.0, 4.0, 16.0, 64.0};
       const int nkc = kcut_cost > 0 ? 1 : 4;
-      const int forced = env_tile(tile_env, 4, -1);
+      const int forced = force_tile >= 0 ? force_tile : env_tile(tile_env, 4, -1);
       const double work = (double)n * (double)mu * (double)k;
       double bestc = 1e300;
       for (int ik = 0; ik < nkc; ++ik) {
@@ -429,6 +430,7 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
       else if (fam == 1) tile = choose_bool_tile(pcs);
       else tile = choose_ring_tile(pcs, prec);
       tile = env_tile(tile_env, fam == 2 ? 5 : 4, tile);
+      if (force_tile >= 0) tile = force_tile;
     }
   } else {
     if (fam == 0) {
@@ -521,8 +523,6 @@ extern "C" paco_status paco_plan_export(int64_t n, int64_t m, int64_t k, paco_se
   return PACO_OK;
 }
 
-paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res);
-
 extern "C" paco_status paco_semiring_mm(paco_ctx ctx, int64_t n, int64_t m, int64_t k,
                                         paco_semiring sr, const void* A, const void* B, void* C) {
   paco_mm_desc d;
@@ -543,7 +543,14 @@ extern "C" paco_status paco_semiring_mm_ex(paco_ctx ctx, const paco_mm_desc* d, 
   return run_mm(ctx, d, res);
 }
 
-paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
+std::string paco::tune_key(const paco_mm_desc* d, int prec) {
+  char key[128];
+  snprintf(key, sizeof key, "%d/%lld/%lld/%lld/%d", (int)d->sr, (long long)d->n, (long long)d->m, (long long)d->k,
+           prec);
+  return key;
+}
+
+paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res, int force_tile) {
   if (res) {
     memset(res, 0, sizeof *res);
     res->verify_max_rel = -1;
@@ -605,14 +612,27 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   }
   const double* weights = d->weights;
   int p = d->p > 0 ? d->p : (d->part != PACO_PART_GRID ? 0 : ctx->num_cus);
-  if (!weights && d->p == 0 && d->part == PACO_PART_PACO && d->sr == PACO_SR_PLUS_TIMES_F32 &&
-      (int)ctx->weights.size() == ctx->num_cus) {
+  int part = (int)d->part;
+  double kc_in = d->kcut_cost;
+  bool use_ctx_weights = d->sr == PACO_SR_PLUS_TIMES_F32 && (int)ctx->weights.size() == ctx->num_cus;
+  if (force_tile < 0 && d->part == PACO_PART_PACO && d->p == 0 && d->kcut_cost == 0 && !d->weights &&
+      !ctx->tuned.empty()) {
+    auto it = ctx->tuned.find(tune_key(d, z.prec));
+    if (it != ctx->tuned.end()) {   // paco_tune measured this shape
+      part = it->second.part;
+      p = it->second.p;
+      kc_in = it->second.kcut;
+      force_tile = it->second.tile;
+      use_ctx_weights = use_ctx_weights && it->second.weighted;
+    }
+  }
+  if (!weights && d->p == 0 && part == PACO_PART_PACO && use_ctx_weights) {
     weights = ctx->weights.data();   // the context's measured throughputs
     p = ctx->num_cus;
   }
   uint64_t whash = 0;
   if (weights) {
-    if (d->part != PACO_PART_PACO || p <= 0) {
+    if (part != PACO_PART_PACO || p <= 0) {
       set_err(ctx, "processor weights need PACO mode and an explicit p");
       return PACO_ERR_INVALID_ARG;
     }
@@ -635,20 +655,20 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   // ---- plan
   char key[256];
   // 0 = chosen with the tile and p (VALU semirings, see make_mm_plan)
-  const double kc = d->kcut_cost > 0 ? d->kcut_cost : plan_kcut_cost((int)d->sr);
+  const double kc = kc_in > 0 ? kc_in : plan_kcut_cost((int)d->sr);
   const char* tenv = getenv(is_bool ? "PACO_BOOL_TILE" : (d->sr == PACO_SR_PLUS_TIMES_F32 ? "PACO_RING_TILE"
                                                                                            : "PACO_INT_TILE"));
-  snprintf(key, sizeof key, "mm/%d/%lld/%lld/%lld/%d/%d/%d/%d/%g/%.8s/%llx", (int)d->sr, (long long)z.n,
-           (long long)z.m, (long long)z.k, (int)d->part, p, d->grid_split_k, z.prec, kc, tenv ? tenv : "",
-           (unsigned long long)whash);
+  snprintf(key, sizeof key, "mm/%d/%lld/%lld/%lld/%d/%d/%d/%d/%g/%.8s/%llx/%d", (int)d->sr, (long long)z.n,
+           (long long)z.m, (long long)z.k, part, p, d->grid_split_k, z.prec, kc, tenv ? tenv : "",
+           (unsigned long long)whash, force_tile);
   DevPlan* dp = nullptr;
   auto itp = ctx->plans.find(key);
   if (itp != ctx->plans.end()) {
     dp = itp->second.get();
   } else {
     std::unique_ptr<DevPlan> np(new DevPlan());
-    make_mm_plan((int)d->sr, z.n, z.m, z.k, (int)d->part, p, d->grid_split_k, z.prec, ctx->num_cus,
-                 np.get(), kc, weights);
+    make_mm_plan((int)d->sr, z.n, z.m, z.k, part, p, d->grid_split_k, z.prec, ctx->num_cus, np.get(), kc, weights,
+                 force_tile);
     paco_status st = upload_plan(ctx, np.get());
     if (st != PACO_OK) return st;
     dp = np.get();
@@ -689,7 +709,7 @@ paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res) {
   }
   if (res) {
     res->precision = (paco_precision)(z.prec < 0 ? PACO_PREC_FP32 : z.prec);
-    res->p = d->part != PACO_PART_GRID ? dp->p : dp->h.nwg;
+    res->p = part != PACO_PART_GRID ? dp->p : dp->h.nwg;
     res->n_pieces = dp->h.n_pieces;
     res->max_piece_volume = dp->h.vmax;
     res->min_piece_volume = dp->h.vmin;

@@ -34,6 +34,12 @@ struct paco_ctx_s {
   hipStream_t stream = nullptr;
   int num_cus = 0;
   std::vector<double> weights;   // processor throughputs for default-p ring calls (paco_set_processor_weights)
+  struct Tuned {                 // paco_tune's choice for a shape, used by default calls
+    int part = 0, p = 0, tile = -1;
+    double kcut = 0.0;
+    bool weighted = false;
+  };
+  std::map<std::string, Tuned> tuned;
   uint64_t budget = 0;
   void* ws = nullptr;        // temporary faces
   uint64_t ws_bytes = 0;
@@ -46,6 +52,7 @@ struct paco_ctx_s {
   std::string last_error;
   // per-kernel timing (paco_timing_enable)
   bool timing = false;
+  uint64_t ws_gen = 0;   // bumped whenever ws or sws is (re)allocated: captured graphs check it
   struct Mark {
     hipEvent_t a, b;
     int role;  // 0 main, 1 reduce, 2 other
@@ -71,9 +78,14 @@ int64_t words(int64_t bits);
 int auto_precision(int64_t k);
 bool ring_vec_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t m, int64_t k);
 void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
-                  int num_cus, DevPlan* np, double kcut_cost, const double* weights = nullptr);
+                  int num_cus, DevPlan* np, double kcut_cost, const double* weights = nullptr,
+                  int force_tile = -1);
 double default_kcut_cost(int sr);
 double plan_kcut_cost(int sr);
+// The semiring MM call; force_tile >= 0 fixes the kernel tile (tuning).
+paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res, int force_tile = -1);
+// key of paco_tune's choices
+std::string tune_key(const paco_mm_desc* d, int prec);
 
 // Brackets one kernel launch with timing events when timing is enabled.
 struct TimeScope {

@@ -35,6 +35,7 @@ paco_status ensure_sws(paco_ctx ctx, uint64_t bytes) {
     ctx->sws = nullptr;
     ctx->sws_bytes = 0;
   }
+  ctx->ws_gen += 1;
   if ((e = hipMalloc(&ctx->sws, bytes)) != hipSuccess) return hip_fail(ctx, e, "Strassen workspace alloc");
   ctx->sws_bytes = bytes;
   return PACO_OK;
