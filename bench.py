@@ -276,6 +276,7 @@ def main():
     ap.add_argument("--server-requests", type=int, default=4096)
     ap.add_argument("--no-calibrate", action="store_true",
                     help="ring workloads: skip the measured processor throughputs (equal weights)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the hipGraph replay timing")
     ap.add_argument("--hold", type=float, default=0.0,
                     help="after the JSON line, keep running the step for this many seconds "
                          "(for sampling clocks and power from outside)")
@@ -345,6 +346,24 @@ def main():
     work, unit, bound, peak = algorithmic(w, prec)
     achieved = work / (kern_ms * 1e-3) / 1e12
     value = classic_ops(w) / (ms * 1e-3) / 1e9
+
+    # ---- the same step captured once into a hipGraph and replayed
+    graph = None
+    if not args.no_graph and not (w["kind"] == "strassen" and w["mode"] != "pbfs"):
+        if w["kind"] == "strassen":
+            G = ctx.graph_strassen(Ad, Bd, C, p=w["p"], gamma=w["gamma"], base=w["base"], leaf=w["prec"])
+        elif w["kind"] == "bool":
+            G = ctx.graph(Ad, Bd, "bool", n=w["n"], m=w["m"], k=w["k"], C=C)
+        elif w["kind"] == "ring":
+            G = ctx.graph(Ad, Bd, "ring", C=C, precision=w["prec"])
+        else:
+            G = ctx.graph(Ad, Bd, w["kind"], C=C)
+        for _ in range(3):
+            G.launch()
+        gms = timed(torch, G.launch, args.steps) * 1e3
+        G.close()
+        graph = {"ms_per_step": round(gms, 4), "value": round(classic_ops(w) / (gms * 1e-3) / 1e9, 3)}
+        log(f"graph replay: {gms:.4f} ms/step")
 
     # ---- Strassen: the classic product on the same operands (PACO ring path)
     classic = None
@@ -435,6 +454,7 @@ def main():
                      "other_ms": round(other_ms, 4), "work_per_launch": work},
         "grid_baseline": grid,
         "paco_vs_grid": round(grid["ms_per_step"] / ms, 4) if grid else None,
+        "graph_replay": graph,
         "classic_baseline": classic,
         "strassen_vs_classic": round(classic["ms_per_step"] / ms, 4) if classic else None,
         "error": err,
