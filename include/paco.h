@@ -277,8 +277,11 @@ paco_status paco_tune_clear(paco_ctx ctx);
 
 /* A call captured once and replayed.  paco_graph_create runs the call
  * eagerly on the context stream (building and uploading its plan, sizing
- * the workspace), waits for it, then records the same call's kernel
- * launches into a hipGraph on a private stream and instantiates it.
+ * the workspace), waits for it, then records `repeat` (1..4096)
+ * back-to-back runs of the call's kernel launches into a hipGraph on a
+ * private stream and instantiates it.  Each graph launch carries a fixed
+ * cost (measured 5-100 us on ROCm 7.2), so capturing several runs pays off
+ * for short calls.
  * paco_graph_launch replays those launches on `stream` (a hipStream_t as an
  * opaque pointer; NULL = the context stream) with the operand pointers and
  * sizes of the capture, reading whatever the buffers hold at replay time.
@@ -290,8 +293,9 @@ paco_status paco_tune_clear(paco_ctx ctx);
  * on one stream are ordered; replays that overlap with other calls on the
  * same context race on its workspace. */
 typedef struct paco_graph_s* paco_graph;
-paco_status paco_graph_create(paco_ctx ctx, const paco_mm_desc* d, paco_graph* out);
-paco_status paco_graph_create_strassen(paco_ctx ctx, const paco_strassen_desc* d, paco_graph* out);
+paco_status paco_graph_create(paco_ctx ctx, const paco_mm_desc* d, int32_t repeat, paco_graph* out);
+paco_status paco_graph_create_strassen(paco_ctx ctx, const paco_strassen_desc* d, int32_t repeat,
+                                       paco_graph* out);
 paco_status paco_graph_launch(paco_graph g, void* stream);
 paco_status paco_graph_destroy(paco_graph g);
 

@@ -161,8 +161,9 @@ def lib():
     L.paco_calibrate.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp]
     L.paco_tune.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(TuneResult)]
     L.paco_tune_clear.argtypes = [vp]
-    L.paco_graph_create.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(vp)]
-    L.paco_graph_create_strassen.argtypes = [vp, ctypes.POINTER(StrassenDesc), ctypes.POINTER(vp)]
+    L.paco_graph_create.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.c_int32, ctypes.POINTER(vp)]
+    L.paco_graph_create_strassen.argtypes = [vp, ctypes.POINTER(StrassenDesc), ctypes.c_int32,
+                                             ctypes.POINTER(vp)]
     L.paco_graph_launch.argtypes = [vp, vp]
     L.paco_graph_destroy.argtypes = [vp]
     L.paco_set_processor_weights.argtypes = [vp, ctypes.c_int32, vp]
@@ -338,18 +339,19 @@ class Context:
     def tune_clear(self):
         _check(self._L.paco_tune_clear(self._h), self._h)
 
-    def graph(self, A, B, semiring="ring", **kw):
-        """Capture C = A (x) B (same arguments as semiring_mm, C required)
-        into a hipGraph; returns a Graph whose launch() replays it."""
+    def graph(self, A, B, semiring="ring", repeat=1, **kw):
+        """Capture `repeat` runs of C = A (x) B (same arguments as
+        semiring_mm, C required) into a hipGraph; returns a Graph whose
+        launch() replays them."""
         if kw.get("C") is None:
             raise ValueError("a captured call needs its output buffer C")
         d, keep = self._desc(A, B, semiring, **kw)
         self._stream()
         h = ctypes.c_void_p()
-        _check(self._L.paco_graph_create(self._h, ctypes.byref(d), ctypes.byref(h)), self._h)
+        _check(self._L.paco_graph_create(self._h, ctypes.byref(d), repeat, ctypes.byref(h)), self._h)
         return Graph(self, h, (A, B, kw["C"], keep))
 
-    def graph_strassen(self, A, B, C, p=0, gamma=0, base=0, leaf="bf16x3"):
+    def graph_strassen(self, A, B, C, p=0, gamma=0, base=0, leaf="bf16x3", repeat=1):
         """Capture a pruned-BFS Strassen call into a hipGraph."""
         for t, nm in ((A, "A"), (B, "B"), (C, "C")):
             self._check_tensor(t, nm, torch.float32)
@@ -360,7 +362,7 @@ class Context:
         d = StrassenDesc(n, _ptr(A), _ptr(B), _ptr(C), p, gamma, base, PRECISION[leaf])
         self._stream()
         h = ctypes.c_void_p()
-        _check(self._L.paco_graph_create_strassen(self._h, ctypes.byref(d), ctypes.byref(h)), self._h)
+        _check(self._L.paco_graph_create_strassen(self._h, ctypes.byref(d), repeat, ctypes.byref(h)), self._h)
         return Graph(self, h, (A, B, C))
 
     def _desc(self, A, B, semiring="ring", *, n=None, m=None, k=None, C=None, accumulate=False,

@@ -23,7 +23,7 @@ struct paco_graph_s {
 namespace {
 
 template <class F>
-paco_status capture(paco_ctx ctx, F call, paco_graph* out) {
+paco_status capture(paco_ctx ctx, F call, int repeat, paco_graph* out) {
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   // eager run: plans, uploads and workspace growth happen here, not in the
@@ -41,7 +41,7 @@ paco_status capture(paco_ctx ctx, F call, paco_graph* out) {
   hipGraph_t g = nullptr;
   e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    st = call();
+    for (int r = 0; r < repeat && st == PACO_OK; ++r) st = call();
     hipError_t e2 = hipStreamEndCapture(cs, &g);
     if (e2 != hipSuccess && st == PACO_OK) {
       e = e2;
@@ -72,22 +72,23 @@ paco_status capture(paco_ctx ctx, F call, paco_graph* out) {
 
 }  // namespace
 
-extern "C" paco_status paco_graph_create(paco_ctx ctx, const paco_mm_desc* d, paco_graph* out) {
-  if (!ctx || !d || !out) return PACO_ERR_INVALID_ARG;
+extern "C" paco_status paco_graph_create(paco_ctx ctx, const paco_mm_desc* d, int32_t repeat, paco_graph* out) {
+  if (!ctx || !d || !out || repeat < 1 || repeat > 4096) return PACO_ERR_INVALID_ARG;
   *out = nullptr;
   if (d->verify_rows != 0) {
     set_err(ctx, "a captured call cannot verify (it synchronises)");
     return PACO_ERR_INVALID_ARG;
   }
   paco_mm_desc dc = *d;
-  return capture(ctx, [&] { return paco_semiring_mm_ex(ctx, &dc, nullptr); }, out);
+  return capture(ctx, [&] { return paco_semiring_mm_ex(ctx, &dc, nullptr); }, repeat, out);
 }
 
-extern "C" paco_status paco_graph_create_strassen(paco_ctx ctx, const paco_strassen_desc* d, paco_graph* out) {
-  if (!ctx || !d || !out) return PACO_ERR_INVALID_ARG;
+extern "C" paco_status paco_graph_create_strassen(paco_ctx ctx, const paco_strassen_desc* d, int32_t repeat,
+                                                  paco_graph* out) {
+  if (!ctx || !d || !out || repeat < 1 || repeat > 4096) return PACO_ERR_INVALID_ARG;
   *out = nullptr;
   paco_strassen_desc dc = *d;
-  return capture(ctx, [&] { return paco_strassen_pbfs(ctx, &dc, nullptr); }, out);
+  return capture(ctx, [&] { return paco_strassen_pbfs(ctx, &dc, nullptr); }, repeat, out);
 }
 
 extern "C" paco_status paco_graph_launch(paco_graph g, void* stream) {

@@ -134,3 +134,21 @@ def test_tune_then_default_calls_stay_exact(ctx, sr):
     if r["tuned"]:
         assert res["p"] == r["p"] and res["kcut_cost"] == r["kcut_cost"]
     ctx.tune_clear()
+
+
+def test_graph_repeat_runs_every_call(ctx):
+    # accumulate mode makes every captured run visible: C = C0 + r * A B
+    print("case: graph repeat=5 ring accumulate", flush=True)
+    A, B = workloads.small_int_operands(300, 200, 700, seed=28)
+    AB = A.astype(np.int64) @ B.astype(np.int64)
+    Ad, Bd = dev(A), dev(B)
+    C = torch.zeros((300, 200), device=DEV)
+    g = ctx.graph(Ad, Bd, "ring", C=C, precision="bf16x3", accumulate=True, repeat=5)
+    # the eager warm-up call accumulated once
+    assert np.array_equal(host(C).astype(np.int64), AB)
+    for rep in range(2):
+        C.zero_()
+        torch.cuda.synchronize()
+        g.launch()
+        assert np.array_equal(host(C).astype(np.int64), 5 * AB), rep
+    g.close()
