@@ -341,8 +341,13 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
     po.kcut_cost = kcut_cost;
     po.max_rounds = 4;
     po.weights = weights;   // explicit p only (checked by the caller)
+    // weighted ratio cuts land anywhere on the quantum grid; for the ring
+    // kernel's 256-wide tiles an n or m cut off that grid pads every tile
+    // it crosses, so weighted ring cuts in n and m stay on tile multiples
+    // (k cuts keep the 32-deep step)
+    const bool wring = weights && fam == 2;
     if (fam == 1) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
-    else if (fam == 2) { po.q[0] = 16; po.q[1] = 16; po.q[2] = 32; }
+    else if (fam == 2) { po.q[0] = wring ? 256 : 16; po.q[1] = wring ? 256 : 16; po.q[2] = 32; }
     auto part_for = [&](int pp) {
       po.p = pp;
       std::vector<Piece> v = part == PACO_PART_MULTI ? partition_multi(n, m, k, po) : partition_mm1(n, m, k, po);
