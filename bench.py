@@ -174,9 +174,9 @@ def cpu_baseline(w, A, B, target_s):
         elif kind == "bool":
             oracle.bool_packed(A[idx].view(np.uint32), B.view(np.uint32), rows, m, k)
         dt = time.perf_counter() - t0
-        if dt >= target_s / 4 or rows >= n:
+        if dt >= target_s / 2 or rows >= n:
             break
-        rows = min(n, int(rows * max(2.0, target_s / max(dt, 1e-3) / 1.5)))
+        rows = min(n, int(rows * max(2.0, 1.1 * target_s / max(dt, 1e-3))))
     ops = 2.0 * rows * m * k   # same unit as the GPU value: one (x) and one (+) per (i, j, l)
     return {"value": ops / dt / 1e9, "unit": "GOP/s", "cores": thr, "kind": "oracle",
             "sample": f"{rows} of {n} output rows (full width), float64/int64 triple loop, "
