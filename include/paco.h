@@ -187,6 +187,23 @@ paco_status paco_semiring_mm_ex(paco_ctx ctx, const paco_mm_desc* d, paco_mm_res
  * in bf16 TFLOP/s.  iters = 0: about 50 ms per run.  Synchronous. */
 paco_status paco_calibrate(paco_ctx ctx, int32_t p, int32_t iters, double* rates);
 
+/* Measured peaks of this device, for the rooflines' denominators:
+ *   PACO_PEAK_MFMA_BF16  bf16 matrix-core products (32x32x16), TFLOP/s
+ *   PACO_PEAK_VALU_I32   u32 add and min vector instructions, T lane-instr/s
+ *   PACO_PEAK_VALU_F32   fp32 fused multiply-adds (unpacked), TFLOP/s
+ *   PACO_PEAK_HBM_COPY   1 GiB device-to-device copy, GB/s (read + written)
+ * Each probe runs twice on the context stream (the first untimed) with four
+ * workgroups per compute unit and is timed between events; it allocates
+ * and frees its own buffers (2 GiB for the copy).  Synchronous.  Unknown
+ * kind: PACO_ERR_INVALID_ARG. */
+typedef enum {
+  PACO_PEAK_MFMA_BF16 = 0,
+  PACO_PEAK_VALU_I32 = 1,
+  PACO_PEAK_VALU_F32 = 2,
+  PACO_PEAK_HBM_COPY = 3
+} paco_peak_kind;
+paco_status paco_peak(paco_ctx ctx, paco_peak_kind kind, double* rate);
+
 /* Keep p processor throughputs in the context (copied): from then on ring
  * calls in PACO mode that leave p and weights at 0 run on p processors with
  * the heterogeneous split.  p = 0 or weights = NULL clears them.  p must be

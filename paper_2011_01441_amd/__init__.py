@@ -167,6 +167,7 @@ def lib():
     L.paco_graph_launch.argtypes = [vp, vp]
     L.paco_graph_destroy.argtypes = [vp]
     L.paco_set_processor_weights.argtypes = [vp, ctypes.c_int32, vp]
+    L.paco_peak.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     L.paco_strassen_pbfs.argtypes = [vp, ctypes.POINTER(StrassenDesc), ctypes.POINTER(StrassenResult)]
     L.paco_strassen_schedule.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, i64,
                                          ctypes.POINTER(StrassenLevel), ctypes.c_int32,
@@ -457,6 +458,16 @@ class Context:
         self._stream()
         _check(self._L.paco_calibrate(self._h, p, iters, ctypes.c_void_p(r.ctypes.data)), self._h)
         return r
+
+    def peak(self, kind):
+        """Measured peak of this device: "mfma_bf16" (TFLOP/s), "valu_i32"
+        (T lane-instructions/s of u32 add and min), "valu_f32" (TFLOP/s of
+        unpacked FMA) or "hbm_copy" (GB/s read + written)."""
+        kinds = {"mfma_bf16": 0, "valu_i32": 1, "valu_f32": 2, "hbm_copy": 3}
+        r = ctypes.c_double(0.0)
+        self._stream()
+        _check(self._L.paco_peak(self._h, kinds[kind], ctypes.byref(r)), self._h)
+        return r.value
 
     def set_processor_weights(self, weights=None):
         """Default-p ring calls in PACO mode use these throughputs (one per

@@ -74,3 +74,83 @@ extern "C" paco_status paco_set_processor_weights(paco_ctx ctx, int32_t p, const
   ctx->weights.assign(weights, weights + p);
   return PACO_OK;
 }
+
+namespace {
+
+// runs `launch` twice (the first untimed) and returns the seconds of the
+// second run between events on the context stream
+template <class F>
+hipError_t time_twice(paco_ctx ctx, F launch, double* sec) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  *sec = ms * 1e-3;
+  return e;
+}
+
+}  // namespace
+
+extern "C" paco_status paco_peak(paco_ctx ctx, paco_peak_kind kind, double* rate) {
+  if (!ctx || !rate) return PACO_ERR_INVALID_ARG;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  const int nwg = 4 * ctx->num_cus;   // four workgroups (16 waves) per compute unit
+  double sec = 0, work = 0;
+  void* buf = nullptr;
+  switch (kind) {
+    case PACO_PEAK_MFMA_BF16: {
+      const int it = 100000;
+      if ((e = hipMalloc(&buf, sizeof(uint64_t) * 2 * nwg + 1024)) != hipSuccess) break;
+      uint64_t* st = (uint64_t*)buf;
+      float* sink = (float*)(st + 2 * nwg);
+      e = time_twice(ctx, [&] { return launch_calib(nwg, it, st, sink, ctx->stream); }, &sec);
+      work = (double)nwg * it * 4 * 4 * 2.0 * 32 * 32 * 16;   // flops
+      break;
+    }
+    case PACO_PEAK_VALU_I32: {
+      const int it = 100000;
+      if ((e = hipMalloc(&buf, 1024)) != hipSuccess) break;
+      e = time_twice(ctx, [&] { return launch_peak_valu_i32(nwg, it, (uint32_t*)buf, ctx->stream); }, &sec);
+      work = (double)nwg * 256 * it * 8 * 2;   // lane-instructions
+      break;
+    }
+    case PACO_PEAK_VALU_F32: {
+      const int it = 100000;
+      if ((e = hipMalloc(&buf, 1024)) != hipSuccess) break;
+      e = time_twice(ctx, [&] { return launch_peak_valu_f32(nwg, it, (float*)buf, ctx->stream); }, &sec);
+      work = (double)nwg * 256 * it * 8 * 2;   // flops (one FMA = 2)
+      break;
+    }
+    case PACO_PEAK_HBM_COPY: {
+      const int64_t bytes = (int64_t)1 << 30;
+      if ((e = hipMalloc(&buf, 2 * bytes)) != hipSuccess) break;
+      char* src = (char*)buf;
+      char* dst = src + bytes;
+      if ((e = hipMemsetAsync(src, 1, bytes, ctx->stream)) != hipSuccess) break;
+      e = time_twice(ctx, [&] { return launch_peak_copy(src, dst, bytes, 8 * ctx->num_cus, ctx->stream); }, &sec);
+      work = 2.0 * bytes;   // bytes read + written
+      break;
+    }
+    default:
+      set_err(ctx, "peak: unknown kind");
+      return PACO_ERR_INVALID_ARG;
+  }
+  if (buf) (void)hipFree(buf);
+  if (e != hipSuccess) return hip_fail(ctx, e, "peak probe");
+  if (!(sec > 0)) {
+    set_err(ctx, "peak: non-positive duration");
+    return PACO_ERR_INTERNAL;
+  }
+  *rate = work / sec / (kind == PACO_PEAK_HBM_COPY ? 1e9 : 1e12);
+  return PACO_OK;
+}
+

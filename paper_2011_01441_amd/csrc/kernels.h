@@ -79,5 +79,8 @@ hipError_t launch_strassen_combine_batch(int levels, int64_t n, int nb, const fl
 // (100 MHz real-time counter) to stamps[2w], stamps[2w+1].  `sink` (256
 // floats) is never written in practice.
 hipError_t launch_calib(int nwg, int iters, uint64_t* stamps, float* sink, hipStream_t s);
+hipError_t launch_peak_valu_i32(int nwg, int iters, uint32_t* sink, hipStream_t s);
+hipError_t launch_peak_valu_f32(int nwg, int iters, float* sink, hipStream_t s);
+hipError_t launch_peak_copy(const void* src, void* dst, int64_t bytes, int nwg, hipStream_t s);
 
 }  // namespace paco
