@@ -131,12 +131,13 @@ extern "C" paco_status paco_peak(paco_ctx ctx, paco_peak_kind kind, double* rate
       break;
     }
     case PACO_PEAK_HBM_COPY: {
+      const int cwg = 4 * ctx->num_cus;
       const int64_t bytes = (int64_t)1 << 30;
       if ((e = hipMalloc(&buf, 2 * bytes)) != hipSuccess) break;
       char* src = (char*)buf;
       char* dst = src + bytes;
       if ((e = hipMemsetAsync(src, 1, bytes, ctx->stream)) != hipSuccess) break;
-      e = time_twice(ctx, [&] { return launch_peak_copy(src, dst, bytes, 8 * ctx->num_cus, ctx->stream); }, &sec);
+      e = time_twice(ctx, [&] { return launch_peak_copy(src, dst, bytes, cwg, ctx->stream); }, &sec);
       work = 2.0 * bytes;   // bytes read + written
       break;
     }
