@@ -5,8 +5,9 @@ the benchmark's CPU-baseline leg.  The GPU library never imports it, and it
 imports nothing from the GPU library.
 
 Every function is a thin numpy/ctypes wrapper over `oracle.c`, which holds
-the plain definitions (section "PACO MM" problem statement and section
-"PACO Strassen" formulas); see that file's header for the semiring readings.
+the plain definitions (section "PACO MM" problem statement, section "PACO
+Strassen" formulas and section "PACO 1D", equation (1D)); see that file's
+header for the semiring readings.
 """
 import ctypes
 import os
@@ -38,6 +39,13 @@ def lib():
         L.oracle_ring_i64.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64]
         L.oracle_strassen_f64.argtypes = [i64, vp, vp, vp, ci]
         L.oracle_strassen_i64.argtypes = [i64, vp, vp, vp, ci]
+        L.oracle_fmix32.argtypes = [ctypes.c_uint32]
+        L.oracle_fmix32.restype = ctypes.c_uint32
+        L.oracle_dp1d_w.argtypes = [ci, i64, i64, ctypes.c_uint32, i64, i64]
+        L.oracle_dp1d_w.restype = i64
+        L.oracle_dp1d.argtypes = [i64, ci, i64, i64, ctypes.c_uint32, vp]
+        L.oracle_dp1d_check.argtypes = [ci, i64, i64, ctypes.c_uint32, vp, vp, i64]
+        L.oracle_dp1d_check.restype = i64
         L.oracle_num_threads.restype = ci
         _lib = L
     return _lib
@@ -148,6 +156,35 @@ def strassen_i64(A, B, levels):
     C = np.empty((n, n), np.int64)
     lib().oracle_strassen_i64(n, _p(A), _p(B), _p(C), int(levels))
     return C
+
+
+W_KIND = {"affine": 0, "hash": 1}
+
+
+def fmix32(h):
+    return lib().oracle_fmix32(int(h) & 0xFFFFFFFF)
+
+
+def dp1d_w(kind, a, b, seed, i, j):
+    """The weight w(i, j) of the 1D problem (see oracle.c)."""
+    return lib().oracle_dp1d_w(W_KIND[kind], a, b, int(seed) & 0xFFFFFFFF, i, j)
+
+
+def dp1d(n, kind, a, b, seed=0, d0=0):
+    """D[0..n] of the 1D problem, D[0] = d0 (section "PACO 1D")."""
+    D = np.empty(n + 1, np.int32)
+    D[0] = d0
+    lib().oracle_dp1d(n, W_KIND[kind], a, b, int(seed) & 0xFFFFFFFF, _p(D))
+    return D
+
+
+def dp1d_check(D, js, kind, a, b, seed=0):
+    """How many of the listed j do not satisfy the recurrence over the given
+    D[0..j-1]."""
+    D = np.ascontiguousarray(D, np.int32)
+    js = np.ascontiguousarray(js, np.int64)
+    assert js.size == 0 or (js.min() >= 0 and js.max() < D.size)
+    return lib().oracle_dp1d_check(W_KIND[kind], a, b, int(seed) & 0xFFFFFFFF, _p(D), _p(js), js.size)
 
 
 def unpack_bits(W, cols):

@@ -265,6 +265,75 @@ void oracle_strassen_i64(int64_t n, const int64_t* A, const int64_t* B,
   strassen_i64_rec(n, A, n, B, n, C, n, levels);
 }
 
+/* ------------------------------------------------------------- 1D problem */
+/* Section "PACO 1D", equation (1D): given D[0] and a weight function w that
+ * needs no memory, D[j] = min over 0 <= i < j of D[i] + w(i, j), j = 1..n.
+ *
+ * Readings (the section states w real-valued and otherwise leaves it open):
+ *   values are integers, with the (min,+) semiring's INF = 2^30 as "no
+ *   path" and saturating sums min(D[i] + w, INF), int64 arithmetic;
+ *   two weight families, both O(1) with no memory access:
+ *     kind 0, affine:  w(i, j) = a + b (j - i), saturated at INF
+ *     kind 1, hashed:  w(i, j) = a + (fmix32(key) mod 2^b) with
+ *                      key = (i * 0x9E3779B9 + j) mod 2^32, XOR seed, and
+ *                      fmix32 the published MurmurHash3 32-bit finaliser
+ *                      (Appleby): h ^= h >> 16; h *= 0x85EBCA6B;
+ *                      h ^= h >> 13; h *= 0xC2B2AE35; h ^= h >> 16.
+ */
+static uint32_t or_fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+uint32_t oracle_fmix32(uint32_t h) { return or_fmix32(h); }
+
+static int64_t dp_w(int kind, int64_t a, int64_t b, uint32_t seed, int64_t i, int64_t j) {
+  int64_t w;
+  if (kind == 0) {
+    w = a + b * (j - i);
+  } else {
+    const uint32_t key = ((uint32_t)i * 0x9E3779B9u + (uint32_t)j) ^ seed;
+    const uint32_t mask = b >= 32 ? 0xFFFFFFFFu : (((uint32_t)1 << b) - 1u);
+    w = a + (int64_t)(or_fmix32(key) & mask);
+  }
+  return w < OR_INF ? w : OR_INF;
+}
+
+int64_t oracle_dp1d_w(int kind, int64_t a, int64_t b, uint32_t seed, int64_t i, int64_t j) {
+  return dp_w(kind, a, b, seed, i, j);
+}
+
+/* min over 0 <= i < j of min(D[i] + w(i, j), INF); INF when j = 0 */
+static int64_t dp1d_at(int kind, int64_t a, int64_t b, uint32_t seed, const int32_t* D, int64_t j) {
+  int64_t acc = OR_INF;
+#pragma omp parallel for reduction(min : acc) if (j > 8192)
+  for (int64_t i = 0; i < j; ++i) {
+    int64_t t = (int64_t)D[i] + dp_w(kind, a, b, seed, i, j);
+    if (t > OR_INF) t = OR_INF;
+    if (t < acc) acc = t;
+  }
+  return acc;
+}
+
+/* D has n + 1 entries: D[0] is read, D[1..n] are written in ascending j. */
+void oracle_dp1d(int64_t n, int kind, int64_t a, int64_t b, uint32_t seed, int32_t* D) {
+  for (int64_t j = 1; j <= n; ++j) D[j] = (int32_t)dp1d_at(kind, a, b, seed, D, j);
+}
+
+/* For each listed j >= 1, whether D[j] equals the recurrence applied to the
+ * given D[0..j-1]; returns how many do not. */
+int64_t oracle_dp1d_check(int kind, int64_t a, int64_t b, uint32_t seed, const int32_t* D,
+                          const int64_t* js, int64_t count) {
+  int64_t bad = 0;
+  for (int64_t t = 0; t < count; ++t)
+    if (js[t] >= 1 && (int64_t)D[js[t]] != dp1d_at(kind, a, b, seed, D, js[t])) ++bad;
+  return bad;
+}
+
 /* Threads an OpenMP loop of this library runs on (1 without OpenMP). */
 int oracle_num_threads(void) {
 #ifdef _OPENMP
