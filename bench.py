@@ -45,6 +45,11 @@ WORKLOADS = {
     "strassen_c3": dict(kind="strassen", n=16384, mode="pbfs", p=8, gamma=0, base=256, prec="bf16x3",
                         desc="PACO Strassen, pruned BFS over 8 processor groups (one per XCD), "
                              "n=16384 f32 U[-1,1], bf16x3 node products"),
+    "dp1d_affine": dict(kind="dp1d", n=1 << 20, wk="affine", a=1, b=3, base=512,
+                        desc="1D problem (least weight subsequence), n=2^20, w(i,j) = 1 + 3 (j - i)"),
+    "dp1d_hash": dict(kind="dp1d", n=1 << 20, wk="hash", a=0, b=20, base=512,
+                      desc="1D problem (least weight subsequence), n=2^20, w(i,j) = MurmurHash3 "
+                           "finaliser of (i, j) mod 2^20"),
     "strassen_c3_levels2": dict(kind="strassen", n=16384, mode="levels", levels=2, prec="bf16x3",
                                 desc="Strassen 2 fixed levels, 49 leaves as one MM-1-Piece batch, "
                                      "n=16384 f32 U[-1,1], bf16x3 leaf"),
@@ -92,6 +97,10 @@ def make_inputs(w, torch, dev):
         A, B = A.view(np.int32), B.view(np.int32)
     elif kind == "strassen":
         A, B = W.strassen_operands(w["n"], seed=0)
+    elif kind == "dp1d":
+        # D[0] = 0; D[1..n] are outputs (the weights need no memory)
+        A = np.zeros(w["n"] + 1, np.int32)
+        B = np.zeros(1, np.int32)
     log(f"inputs generated in {time.time() - t0:.1f}s")
     return A, B, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
 
@@ -117,6 +126,15 @@ def algorithmic(w, prec):
     if kind in ("minplus", "maxplus"):
         # two adds and one min3/max3 per two l
         return 1.5 * w["n"] * w["m"] * w["k"], "T lane-instr/s", "alu", PEAK["valu"]
+    if kind == "dp1d":
+        # per pair (i < j): affine weights fold into one add and half a
+        # min3, as (min,+); hashed weights add the key (add, xor with the
+        # seed), the finaliser (two 16-bit shift-xors, one word-select form
+        # each; a shift and an xor; two multiplies at a quarter of the issue
+        # rate, 4 slots each), the mask and the add of D[i]: 15.5 slots
+        pairs = w["n"] * (w["n"] + 1) / 2
+        per = 1.5 if w["wk"] == "affine" else 15.5
+        return per * pairs, "T lane-instr/s", "alu", PEAK["valu"]
     if kind == "bool":
         # one and-or per (row, bit of k, word of the output row)
         return 1.0 * w["n"] * w["k"] * math.ceil(w["m"] / 32), "T lane-instr/s", "alu", PEAK["valu"]
@@ -126,11 +144,21 @@ def algorithmic(w, prec):
 def classic_ops(w):
     if w["kind"] == "strassen":
         return 2.0 * w["n"] ** 3
+    if w["kind"] == "dp1d":   # one add and one min per pair i < j
+        return float(w["n"]) * (w["n"] + 1)
     return 2.0 * w["n"] * w["m"] * w["k"]
 
 
 def call(ctx, w, Ad, Bd, C, **kw):
     kind = w["kind"]
+    if kind == "dp1d":
+        part = kw.pop("part", "paco")
+        kw.pop("split_k", None)
+        rr = kw.pop("return_result", False)
+        r = ctx.dp1d(Ad, w["wk"], w["a"], w["b"], part=part, base=w["base"], return_result=rr)
+        if rr:
+            r[1]["n_pieces"], r[1]["n_kcuts"], r[1]["kcut_cost"] = r[1]["pieces"], r[1]["atomic_pieces"], None
+        return r
     if kind == "strassen":
         if w["mode"] == "pbfs":
             return ctx.strassen_pbfs(Ad, Bd, C=C, p=w["p"], gamma=w["gamma"], base=w["base"], leaf=w["prec"])
@@ -157,6 +185,20 @@ def cpu_baseline(w, A, B, target_s):
     thr = oracle.num_threads()
     kind = w["kind"]
     n = w["n"]
+    if kind == "dp1d":
+        # the recurrence is sequential in j: the sample is a prefix n_s of
+        # the same instance (work n_s (n_s + 1) / 2 pairs)
+        ns = 4096
+        while True:
+            t0 = time.perf_counter()
+            oracle.dp1d(ns, w["wk"], w["a"], w["b"], 0, 0)
+            dt = time.perf_counter() - t0
+            if dt >= target_s / 2 or ns >= n:
+                break
+            ns = min(n, int(ns * max(1.5, math.sqrt(1.1 * target_s / max(dt, 1e-3)))))
+        return {"value": float(ns) * (ns + 1) / dt / 1e9, "unit": "GOP/s", "cores": thr, "kind": "oracle",
+                "sample": f"the first {ns} of {n} outputs (a prefix of the same instance), {dt:.1f} s",
+                "seconds": dt}
     if kind == "strassen":
         m = k = w["n"]
     else:
@@ -301,6 +343,8 @@ def main():
         C = torch.empty((w["n"], (w["m"] + 31) // 32), dtype=torch.int32, device=dev)
     elif w["kind"] == "strassen":
         C = torch.empty((w["n"], w["n"]), dtype=torch.float32, device=dev)
+    elif w["kind"] == "dp1d":
+        C = None
     else:
         C = torch.empty((w["n"], w["m"]), dtype=Ad.dtype, device=dev)
 
@@ -350,9 +394,12 @@ def main():
     timed(torch, lambda: call(ctx, w, Ad, Bd, C), args.steps)
     tm = ctx.timing()
     ctx.timing(False)
-    kern_ms = tm["main_ms"] / max(tm["launches"], 1)
-    red_ms = tm["reduce_ms"] / max(tm["launches"], 1)
-    other_ms = tm["other_ms"] / max(tm["launches"], 1)
+    # per launch of the dominant kernel; the 1D problem launches its square
+    # kernel once per square, so there the unit is one call (all of them)
+    per = args.steps if w["kind"] == "dp1d" else max(tm["launches"], 1)
+    kern_ms = tm["main_ms"] / per
+    red_ms = tm["reduce_ms"] / per
+    other_ms = tm["other_ms"] / per
     log(f"paco: {ms:.3f} ms/step, kernel {kern_ms:.3f} ms, reduce {red_ms:.3f} ms, other {other_ms:.3f} ms")
     # single warm calls, each bracketed by device synchronisations (so each
     # includes one host round trip): min and median
@@ -366,7 +413,7 @@ def main():
 
     # ---- the same step captured once into a hipGraph and replayed
     graph = None
-    if not args.no_graph and not (w["kind"] == "strassen" and w["mode"] != "pbfs"):
+    if not args.no_graph and w["kind"] != "dp1d" and not (w["kind"] == "strassen" and w["mode"] != "pbfs"):
         # one graph holds `steps` back-to-back steps (a graph launch has a
         # fixed cost of its own); it is replayed twice untimed, then timed once
         rep = args.steps
@@ -399,7 +446,15 @@ def main():
 
     # ---- plain tile grid (same microkernels), tile shape and split-k autotuned
     grid = None
-    if not args.no_grid and w["kind"] != "strassen":
+    if not args.no_grid and w["kind"] == "dp1d":
+        # outputs-only strips (no input cuts), same kernels and base triangles
+        f = lambda: call(ctx, w, Ad, Bd, C, part="grid")
+        f()
+        gms = timed(torch, f, args.steps) * 1e3
+        grid = {"value": classic_ops(w) / (gms * 1e-3) / 1e9, "ms_per_step": round(gms, 4),
+                "tile": None, "split_k": None, "partition": "output strips only"}
+        log(f"grid: {gms:.3f} ms/step")
+    elif not args.no_grid and w["kind"] != "strassen":
         tile_env = {"ring": "PACO_RING_TILE", "bool": "PACO_BOOL_TILE"}.get(w["kind"], "PACO_INT_TILE")
         tiles = {"ring": (4, 0, 1, 2) if prec != "bf16x6" else (0, 1, 2)}.get(w["kind"], (0, 1, 2, 3))
         best = None
@@ -421,6 +476,15 @@ def main():
 
     # ---- accuracy of this result
     err = None
+    if w["kind"] == "dp1d":
+        import oracle
+        call(ctx, w, Ad, Bd, C)
+        Dh = Ad.cpu().numpy()
+        rng = np.random.default_rng(0)
+        js = np.concatenate([np.arange(1, 65), rng.integers(1, w["n"] + 1, 128), [w["n"]]])
+        bad = oracle.dp1d_check(Dh, js, w["wk"], w["a"], w["b"], 0)
+        err = {"sampled_outputs": int(js.size), "mismatches": int(bad),
+               "check": "each sampled D[j] equals min over i < j of D[i] + w(i, j) on the GPU's own D"}
     if w["kind"] == "ring":
         _, r = call(ctx, w, Ad, Bd, C, verify_rows=args.verify_rows, return_result=True)
         err = {"max_rel_componentwise_sampled": r["verify_max_rel"], "rows": args.verify_rows,
@@ -460,10 +524,12 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"ring": "bf16" if prec != "fp32" else "f32", "strassen": "bf16",
-                  "minplus": "u32", "maxplus": "i32", "bool": "u32"}[w["kind"]],
+                  "minplus": "u32", "maxplus": "i32", "bool": "u32", "dp1d": "u32"}[w["kind"]],
         "data": "synthetic",
         "config": {"workload": args.workload, "desc": w["desc"], "precision": prec,
-                   "partition": "PACO MM-1-Piece", "p": res["p"] if res else None,
+                   "partition": ("PACO 1D: squares cut by the MM-1-Piece rule, base triangles of %d"
+                                 % w["base"]) if w["kind"] == "dp1d" else "PACO MM-1-Piece",
+                   "p": res["p"] if res else None,
                    "kcut_cost": res["kcut_cost"] if res else None,
                    "processor_weights": ("measured per-XCD matrix-core rates, max/min %.4f" %
                                          (rates.max() / rates.min())) if rates is not None else "equal",
@@ -473,7 +539,8 @@ def main():
         "roofline": {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                      "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.workload),
                      "kernel_ms": round(kern_ms, 4), "reduce_ms": round(red_ms, 4),
-                     "other_ms": round(other_ms, 4), "work_per_launch": work},
+                     "other_ms": round(other_ms, 4), "work_per_launch": work,
+                     "launches_per_unit": (tm["launches"] // args.steps) if w["kind"] == "dp1d" else 1},
         "single_call": call_stats,
         "measured_peaks": peaks,
         "grid_baseline": grid,

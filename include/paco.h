@@ -266,6 +266,72 @@ typedef struct paco_strassen_result {
 
 paco_status paco_strassen_pbfs(paco_ctx ctx, const paco_strassen_desc* d, paco_strassen_result* out);
 
+/* ---------------------------------------------------------- 1D problem */
+
+/* The 1D problem (section "PACO 1D", equation (1D)), also known as least
+ * weight subsequence: given D[0], D[j] = min over 0 <= i < j of
+ * D[i] + w(i, j) for j = 1..n, with a weight function that needs no memory:
+ *   PACO_W_AFFINE  w(i, j) = a + b (j - i)                 (a, b >= 0)
+ *   PACO_W_HASH    w(i, j) = a + (fmix32(key) mod 2^b),   0 <= b <= 29,
+ *                  key = (i * 0x9E3779B9 + j) mod 2^32, XOR seed, fmix32
+ *                  MurmurHash3's 32-bit finaliser.
+ * Values are integers with INF = 2^30 as "no path" and saturating sums.
+ * The weights must stay within INF: a + b n <= 2^30 (affine) or
+ * a + 2^b <= 2^30 (hash); otherwise PACO_ERR_UNSUPPORTED.
+ *
+ * The recursion of the section: the positions [0, n] split in halves (cut
+ * points on multiples of 64), the left half is solved, its outputs update
+ * the right half's (a square of inputs by outputs), then the right half is
+ * solved; halves of at most `base` positions are base triangles run by one
+ * workgroup.  part = PACO_PART_PACO cuts each square over
+ * min(p, area / min_piece) processors (at least 1) by the ratio rule of
+ * MM-1-Piece on its longer side (outputs on ties); pieces whose inputs were
+ * cut combine with atomic minima.  PACO_PART_GRID (baseline) splits the
+ * outputs only, into at most that many strips of at least 64.
+ *
+ * D: device array of n + 1 int32, D[0] read (in [0, 2^30]; outside reads as
+ * INF), D[1..n] written.  Asynchronous on the context stream; the plan is
+ * cached per (n, part, p, base, min_piece).  Calls on one context must not
+ * overlap (each plan keeps its own launch counters). */
+typedef enum { PACO_W_AFFINE = 0, PACO_W_HASH = 1 } paco_w_kind;
+
+typedef struct paco_dp1d_desc {
+  int64_t n;
+  int32_t w_kind;      /* paco_w_kind */
+  int32_t a;           /* weight offset */
+  int32_t b;           /* affine slope, or hash bits */
+  uint32_t seed;       /* hash seed */
+  int32_t part;        /* PACO_PART_PACO or PACO_PART_GRID */
+  int32_t p;           /* processors; 0: 4 per compute unit */
+  int32_t base;        /* longest base triangle, 64..1024; 0: 512 */
+  int32_t min_piece;   /* least pairs per piece; 0: 65536 */
+  int32_t* D;
+} paco_dp1d_desc;
+
+typedef struct paco_dp1d_result {
+  int32_t p;             /* processors used */
+  int32_t launches;      /* kernel launches of one call */
+  int64_t triangles;     /* base triangles */
+  int64_t squares;       /* external updates */
+  int64_t pieces;        /* pieces over all squares */
+  int32_t max_pieces;    /* most pieces of one square */
+  int32_t atomic_pieces; /* pieces whose inputs were cut, over all squares */
+} paco_dp1d_result;
+
+paco_status paco_dp1d(paco_ctx ctx, const paco_dp1d_desc* desc, paco_dp1d_result* result);
+
+/* Host-only: the plan paco_dp1d launches for (n, part, p, base, min_piece)
+ * (all explicit here: p >= 1, base in 64..1024, min_piece >= 1).  info[0]
+ * and info[1] give the capacities of `squares` and `pieces` on input (when
+ * they are non-NULL) and their counts on output; info[2] = length of the
+ * first base triangle [0, info[2]); info[3] = number of base triangles.
+ *   squares: 8 int64 each (lo, mid, hi, first piece, piece count, lo and
+ *            length of the base triangle that follows, and how many of the
+ *            first pieces reach into it), in launch order;
+ *   pieces : 5 int64 each (i0, i1, j0, j1, inputs cut). */
+paco_status paco_dp1d_plan_export(int64_t n, int32_t part, int32_t p, int32_t base, int32_t min_piece,
+                                  int64_t* info, int64_t* squares, int64_t* pieces);
+
 /* ------------------------------------------------------------- tuning */
 
 /* Measured choice for one shape.  `d` is a default PACO call (part PACO,

@@ -54,6 +54,22 @@ class MMResult(ctypes.Structure):
                 ("kcut_cost", ctypes.c_double)]
 
 
+class Dp1dDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("w_kind", ctypes.c_int32), ("a", ctypes.c_int32),
+                ("b", ctypes.c_int32), ("seed", ctypes.c_uint32), ("part", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("base", ctypes.c_int32), ("min_piece", ctypes.c_int32),
+                ("D", ctypes.c_void_p)]
+
+
+class Dp1dResult(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("launches", ctypes.c_int32), ("triangles", ctypes.c_int64),
+                ("squares", ctypes.c_int64), ("pieces", ctypes.c_int64), ("max_pieces", ctypes.c_int32),
+                ("atomic_pieces", ctypes.c_int32)]
+
+
+W_KIND = {"affine": 0, "hash": 1}
+
+
 class StrassenDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
                 ("p", ctypes.c_int32), ("gamma", ctypes.c_int32), ("base", ctypes.c_int64),
@@ -169,6 +185,9 @@ def lib():
     L.paco_set_processor_weights.argtypes = [vp, ctypes.c_int32, vp]
     L.paco_peak.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     L.paco_strassen_pbfs.argtypes = [vp, ctypes.POINTER(StrassenDesc), ctypes.POINTER(StrassenResult)]
+    L.paco_dp1d.argtypes = [vp, ctypes.POINTER(Dp1dDesc), ctypes.POINTER(Dp1dResult)]
+    L.paco_dp1d_plan_export.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        vp, vp, vp]
     L.paco_strassen_schedule.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, i64,
                                          ctypes.POINTER(StrassenLevel), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32), vp, vp]
@@ -222,6 +241,22 @@ def strassen_schedule(n, p, gamma=0, base=256):
                                     ctypes.c_void_p(wc.ctypes.data), ctypes.c_void_p(wsr.ctypes.data)))
     levels = [{f[0]: getattr(lv[i], f[0]) for f in StrassenLevel._fields_} for i in range(nl.value)]
     return levels, wc, wsr
+
+
+def dp1d_plan(n, part="paco", p=1024, base=512, min_piece=65536):
+    """Host-only: the plan of paco_dp1d.  Returns (first_len, triangles,
+    squares, pieces): squares an (S, 8) int64 array (lo, mid, hi, first
+    piece, piece count, tri_lo, tri_len, pieces reaching the triangle),
+    pieces a (P, 5) int64 array (i0, i1, j0, j1, inputs cut)."""
+    import numpy as np
+    L = lib()
+    info = np.zeros(4, np.int64)
+    vp = lambda a: ctypes.c_void_p(a.ctypes.data)
+    _check(L.paco_dp1d_plan_export(n, PART[part], p, base, min_piece, vp(info), None, None))
+    sq = np.zeros((max(int(info[0]), 1), 8), np.int64)
+    pc = np.zeros((max(int(info[1]), 1), 5), np.int64)
+    _check(L.paco_dp1d_plan_export(n, PART[part], p, base, min_piece, vp(info), vp(sq), vp(pc)))
+    return int(info[2]), int(info[3]), sq[:int(info[0])], pc[:int(info[1])]
 
 
 def partition(n, m, k, p, q=(1, 1, 1), weights=None, multi_piece=False, kcut_cost=1.0, max_rounds=0):
@@ -478,6 +513,22 @@ class Context:
             return
         w = np.ascontiguousarray(weights, np.float64)
         _check(self._L.paco_set_processor_weights(self._h, len(w), ctypes.c_void_p(w.ctypes.data)), self._h)
+
+    def dp1d(self, D, kind, a, b, seed=0, part="paco", p=0, base=0, min_piece=0, return_result=False):
+        """The 1D problem (section "PACO 1D") in place on D, an int32 tensor
+        of n + 1 entries: D[0] is read, D[1..n] are written."""
+        if not isinstance(D, torch.Tensor) or D.device.type != "cuda" or D.device.index != self.device:
+            raise ValueError(f"D must be a tensor on cuda:{self.device}")
+        if D.dtype != torch.int32 or D.dim() != 1 or not D.is_contiguous() or D.numel() < 1:
+            raise ValueError("D must be a contiguous 1-D int32 tensor of n + 1 entries")
+        d = Dp1dDesc(D.numel() - 1, W_KIND[kind], a, b, seed & 0xFFFFFFFF, PART[part], p, base, min_piece,
+                     _ptr(D))
+        r = Dp1dResult()
+        self._stream()
+        _check(self._L.paco_dp1d(self._h, ctypes.byref(d), ctypes.byref(r)), self._h)
+        if return_result:
+            return D, {f[0]: getattr(r, f[0]) for f in Dp1dResult._fields_}
+        return D
 
     def strassen_pbfs(self, A, B, C=None, p=0, gamma=0, base=0, leaf="bf16x3", return_result=False):
         """PACO Strassen with the pruned-BFS schedule over p processor groups

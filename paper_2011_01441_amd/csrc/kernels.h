@@ -78,6 +78,25 @@ hipError_t launch_strassen_combine_batch(int levels, int64_t n, int nb, const fl
 // bf16 matrix-core products per wave; workgroup w writes its start and end
 // (100 MHz real-time counter) to stamps[2w], stamps[2w+1].  `sink` (256
 // floats) is never written in practice.
+// 1D problem (section "PACO 1D"): weight parameters (b is the slope for
+// affine weights, the mask for hashed ones) and one external-update piece
+struct DpW {
+  uint32_t a, b, seed, pad;
+};
+struct DpPiece {
+  int64_t i0, i1, j0, j1;   // inputs [i0, i1) -> outputs [j0, j1)
+  int32_t atomic, pad;      // 1: the inputs were cut, combine with an atomic minimum
+};
+constexpr int DP_TRI_MAX = 1024;   // longest base triangle (one workgroup, LDS)
+// D[1..n] = INF, then the base triangle [0, tri_len); cnt: one zeroed
+// counter (left zeroed)
+hipError_t launch_dp1d_fill(int wk, uint32_t* D, int64_t n, uint32_t* cnt, int tri_len, const DpW& w,
+                            hipStream_t s);
+// one square's pieces, then the base triangle [tri_lo, tri_lo + tri_len),
+// run after the first `ntri` pieces (those reaching into it) have finished
+hipError_t launch_dp1d_rect(int wk, uint32_t* D, const DpPiece* pieces, int npieces, int ntri, uint32_t* cnt,
+                            int64_t tri_lo, int tri_len, const DpW& w, hipStream_t s);
+
 hipError_t launch_calib(int nwg, int iters, uint64_t* stamps, float* sink, hipStream_t s);
 hipError_t launch_peak_valu_i32(int nwg, int iters, uint32_t* sink, hipStream_t s);
 hipError_t launch_peak_valu_f32(int nwg, int iters, float* sink, hipStream_t s);
