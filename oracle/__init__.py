@@ -6,8 +6,8 @@ imports nothing from the GPU library.
 
 Every function is a thin numpy/ctypes wrapper over `oracle.c`, which holds
 the plain definitions (section "PACO MM" problem statement, section "PACO
-Strassen" formulas and section "PACO 1D", equation (1D)); see that file's
-header for the semiring readings.
+Strassen" formulas, section "PACO 1D", equation (1D), and section "PACO
+GAP", equation (gap)); see that file's header for the semiring readings.
 """
 import ctypes
 import os
@@ -46,6 +46,11 @@ def lib():
         L.oracle_dp1d.argtypes = [i64, ci, i64, i64, ctypes.c_uint32, vp]
         L.oracle_dp1d_check.argtypes = [ci, i64, i64, ctypes.c_uint32, vp, vp, i64]
         L.oracle_dp1d_check.restype = i64
+        L.oracle_gap_s.argtypes = [i64, i64, ci, ctypes.c_uint32, ctypes.c_uint32, i64, i64]
+        L.oracle_gap_s.restype = i64
+        L.oracle_gap.argtypes = [i64, i64, vp, vp, vp, vp, i64]
+        L.oracle_gap_check.argtypes = [i64, i64, vp, vp, vp, vp, i64, vp, i64]
+        L.oracle_gap_check.restype = i64
         L.oracle_num_threads.restype = ci
         _lib = L
     return _lib
@@ -185,6 +190,37 @@ def dp1d_check(D, js, kind, a, b, seed=0):
     js = np.ascontiguousarray(js, np.int64)
     assert js.size == 0 or (js.min() >= 0 and js.max() < D.size)
     return lib().oracle_dp1d_check(W_KIND[kind], a, b, int(seed) & 0xFFFFFFFF, _p(D), _p(js), js.size)
+
+
+def _gap_params(wrow, wcol, s):
+    """wrow, wcol: (kind, a, b, seed); s: (s_match, s_mismatch, bits, seed_x, seed_y)."""
+    wr = np.array([W_KIND[wrow[0]], wrow[1], wrow[2], wrow[3] & 0xFFFFFFFF], np.int64)
+    wc = np.array([W_KIND[wcol[0]], wcol[1], wcol[2], wcol[3] & 0xFFFFFFFF], np.int64)
+    sp = np.array([s[0], s[1], s[2], s[3] & 0xFFFFFFFF, s[4] & 0xFFFFFFFF], np.int64)
+    return wr, wc, sp
+
+
+def gap_s(s, i, j):
+    return lib().oracle_gap_s(s[0], s[1], s[2], s[3] & 0xFFFFFFFF, s[4] & 0xFFFFFFFF, i, j)
+
+
+def gap(m, n, wrow, wcol, s, d0=0):
+    """The (m+1) x (n+1) grid of the GAP problem (section "PACO GAP")."""
+    wr, wc, sp = _gap_params(wrow, wcol, s)
+    D = np.empty((m + 1, n + 1), np.int32)
+    D[0, 0] = d0
+    lib().oracle_gap(m, n, _p(wr), _p(wc), _p(sp), _p(D), n + 1)
+    return D
+
+
+def gap_check(D, cells, wrow, wcol, s):
+    """How many listed (i, j) cells do not satisfy the recurrence over the given D."""
+    D = np.ascontiguousarray(D, np.int32)
+    m, n = D.shape[0] - 1, D.shape[1] - 1
+    cells = np.ascontiguousarray(cells, np.int64).reshape(-1, 2)
+    assert cells.size == 0 or (cells[:, 0].max() <= m and cells[:, 1].max() <= n and cells.min() >= 0)
+    wr, wc, sp = _gap_params(wrow, wcol, s)
+    return lib().oracle_gap_check(m, n, _p(wr), _p(wc), _p(sp), _p(D), n + 1, _p(cells), cells.shape[0])
 
 
 def unpack_bits(W, cols):

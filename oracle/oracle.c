@@ -334,6 +334,75 @@ int64_t oracle_dp1d_check(int kind, int64_t a, int64_t b, uint32_t seed, const i
   return bad;
 }
 
+/* -------------------------------------------------------------- GAP problem */
+/* Section "PACO GAP", equation (gap): D[0][0] = d0 and, for 0 <= i <= m,
+ * 0 <= j <= n, (i, j) != (0, 0),
+ *   D[i][j] = min( D[i-1][j-1] + s(i, j)           (i, j >= 1),
+ *                  min over q < j of D[i][q] + w(q, j),
+ *                  min over p < i of D[p][j] + w'(p, i) ),
+ * saturated at INF.  w and w' are weight functions of the 1D problem's two
+ * families (kind, a, b, seed each).  Reading for s (the section only asks
+ * for O(1) with no memory): the substitution cost of two symbol sequences,
+ * x_i = fmix32(i XOR sx) mod 2^bits and y_j = fmix32(j XOR sy) mod 2^bits,
+ * s(i, j) = s_match when x_i = y_j, else s_mismatch.  D is row-major with
+ * leading dimension ld >= n + 1, filled in row-major order (every term is
+ * then already final). */
+static int64_t gap_s(int64_t sm, int64_t sx, int bits, uint32_t seedx, uint32_t seedy, int64_t i, int64_t j) {
+  const uint32_t mask = bits >= 32 ? 0xFFFFFFFFu : (((uint32_t)1 << bits) - 1u);
+  const uint32_t xi = or_fmix32((uint32_t)i ^ seedx) & mask;
+  const uint32_t yj = or_fmix32((uint32_t)j ^ seedy) & mask;
+  return xi == yj ? sm : sx;
+}
+
+int64_t oracle_gap_s(int64_t sm, int64_t sx, int bits, uint32_t seedx, uint32_t seedy, int64_t i, int64_t j) {
+  return gap_s(sm, sx, bits, seedx, seedy, i, j);
+}
+
+/* one cell from its row prefix, column prefix and diagonal neighbour */
+static int64_t gap_cell(int64_t m, int64_t n, const int32_t* D, int64_t ld, int64_t i, int64_t j,
+                        const int64_t* wr, const int64_t* wc, const int64_t* sp) {
+  (void)m; (void)n;
+  int64_t best = OR_INF;
+  if (i >= 1 && j >= 1) {
+    int64_t t = (int64_t)D[(i - 1) * ld + (j - 1)] +
+                gap_s(sp[0], sp[1], (int)sp[2], (uint32_t)sp[3], (uint32_t)sp[4], i, j);
+    if (t < best) best = t;
+  }
+  for (int64_t q = 0; q < j; ++q) {
+    int64_t t = (int64_t)D[i * ld + q] + dp_w((int)wr[0], wr[1], wr[2], (uint32_t)wr[3], q, j);
+    if (t < best) best = t;
+  }
+  for (int64_t p = 0; p < i; ++p) {
+    int64_t t = (int64_t)D[p * ld + j] + dp_w((int)wc[0], wc[1], wc[2], (uint32_t)wc[3], p, i);
+    if (t < best) best = t;
+  }
+  return best < OR_INF ? best : OR_INF;
+}
+
+/* wr, wc: (kind, a, b, seed) of w and w'; sp: (s_match, s_mismatch, bits,
+ * seed x, seed y).  D[0][0] is read; every other entry of the (m+1) x (n+1)
+ * grid is written. */
+void oracle_gap(int64_t m, int64_t n, const int64_t* wr, const int64_t* wc, const int64_t* sp,
+                int32_t* D, int64_t ld) {
+  for (int64_t i = 0; i <= m; ++i)
+    for (int64_t j = 0; j <= n; ++j)
+      if (i != 0 || j != 0) D[i * ld + j] = (int32_t)gap_cell(m, n, D, ld, i, j, wr, wc, sp);
+}
+
+/* how many listed cells (pairs of i, j) differ from the recurrence applied
+ * to the given D */
+int64_t oracle_gap_check(int64_t m, int64_t n, const int64_t* wr, const int64_t* wc, const int64_t* sp,
+                         const int32_t* D, int64_t ld, const int64_t* cells, int64_t count) {
+  int64_t bad = 0;
+#pragma omp parallel for reduction(+ : bad)
+  for (int64_t t = 0; t < count; ++t) {
+    const int64_t i = cells[2 * t], j = cells[2 * t + 1];
+    if (i == 0 && j == 0) continue;
+    if ((int64_t)D[i * ld + j] != gap_cell(m, n, D, ld, i, j, wr, wc, sp)) ++bad;
+  }
+  return bad;
+}
+
 /* Threads an OpenMP loop of this library runs on (1 without OpenMP). */
 int oracle_num_threads(void) {
 #ifdef _OPENMP
