@@ -332,6 +332,78 @@ paco_status paco_dp1d(paco_ctx ctx, const paco_dp1d_desc* desc, paco_dp1d_result
 paco_status paco_dp1d_plan_export(int64_t n, int32_t part, int32_t p, int32_t base, int32_t min_piece,
                                   int64_t* info, int64_t* squares, int64_t* pieces);
 
+/* --------------------------------------------------------- GAP problem */
+
+/* The GAP problem (section "PACO GAP", equation (gap)): edit distance with
+ * gaps.  On the (m+1) x (n+1) grid D (row-major, leading dimension ldd),
+ * D[0][0] given and, for every other cell,
+ *   D[i][j] = min( D[i-1][j-1] + s(i, j)              (i, j >= 1),
+ *                  min over q < j of D[i][q] + w(q, j),
+ *                  min over p < i of D[p][j] + w'(p, i) ),
+ * saturated at INF = 2^30.  w (w_row) and w' (w_col) are weight functions of
+ * the 1D problem's families (paco_w_kind; affine a + b (to - from) with
+ * a + b side <= 2^30, or hashed with b <= 29 bits).  s is the substitution
+ * cost of two symbol sequences over an alphabet of 2^s_bits symbols,
+ * x_i = fmix32(i XOR s_seed_x) mod 2^s_bits, y_j = fmix32(j XOR s_seed_y)
+ * mod 2^s_bits: s_match when x_i = y_j, else s_mismatch (both <= 2^30).
+ *
+ * The recursion of the section: quadrants; the rows of a finished top-left
+ * quadrant update the top-right one, its columns the bottom-left one
+ * (external updates, cubes of batch x inputs x outputs), down to base blocks
+ * of at most 64 x 64 solved by one workgroup.  Independent subproblems share
+ * launches.  part = PACO_PART_PACO cuts every cube among its volume share of
+ * p processors (at least 1, at most volume / min_piece) into slabs of whole
+ * batch rows, the section's rule, so each piece updates outputs of its own
+ * (a batch shorter than the share also cuts the outputs, in multiples of
+ * 64); PACO_PART_GRID (baseline) tiles every cube into 16 batch rows x 256
+ * outputs, whatever p.
+ *
+ * D: device array, caller-owned; D[0][0] read (values outside [0, 2^30]
+ * read as INF), every cell written.  The context keeps a transposed copy of
+ * the grid ((n+1) x (m+1) rounded up to 64, counted against the budget:
+ * PACO_ERR_BUDGET when it does not fit).  Asynchronous on the context
+ * stream; the plan is cached per (m, n, part, p, min_piece). */
+typedef struct paco_weight {
+  int32_t kind;    /* paco_w_kind */
+  int32_t a, b;    /* offset; affine slope or hash bits */
+  uint32_t seed;   /* hash seed */
+} paco_weight;
+
+typedef struct paco_gap_desc {
+  int64_t m, n;              /* grid (m+1) x (n+1) */
+  paco_weight w_row;         /* w(q, j), gaps along a row */
+  paco_weight w_col;         /* w'(p, i), gaps along a column */
+  int32_t s_match, s_mismatch, s_bits;
+  uint32_t s_seed_x, s_seed_y;
+  int32_t part;              /* PACO_PART_PACO or PACO_PART_GRID */
+  int32_t p;                 /* processors; 0: 4 per compute unit */
+  int32_t min_piece;         /* least pairs per piece; 0: 65536 */
+  int32_t* D;
+  int64_t ldd;               /* >= n + 1 */
+} paco_gap_desc;
+
+typedef struct paco_gap_result {
+  int32_t p;                 /* processors used */
+  int32_t launches;          /* kernel launches of one call */
+  int64_t base_blocks;       /* base blocks */
+  int64_t cubes;             /* external updates */
+  int64_t pieces;            /* pieces over all cubes */
+} paco_gap_result;
+
+paco_status paco_gap(paco_ctx ctx, const paco_gap_desc* desc, paco_gap_result* result);
+
+/* Host-only: the plan paco_gap launches for (m, n, part, p, min_piece), all
+ * explicit (p >= 1, min_piece >= 1).  info[0..2] give the capacities of
+ * `launches`, `blocks` and `pieces` on input (when non-NULL) and their counts
+ * on output; info[3] = number of cubes.
+ *   launches: 3 int64 each (1 for base blocks / 0 for cubes, first entry,
+ *             count), in order after the fill;
+ *   blocks  : 4 int64 each (r0, r1, c0, c1);
+ *   pieces  : 7 int64 each (column-gap flag, batch t0, t1, inputs x0, x1,
+ *             outputs o0, o1). */
+paco_status paco_gap_plan_export(int64_t m, int64_t n, int32_t part, int32_t p, int32_t min_piece, int64_t* info,
+                                 int64_t* launches, int64_t* blocks, int64_t* pieces);
+
 /* ------------------------------------------------------------- tuning */
 
 /* Measured choice for one shape.  `d` is a default PACO call (part PACO,

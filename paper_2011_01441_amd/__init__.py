@@ -70,6 +70,28 @@ class Dp1dResult(ctypes.Structure):
 W_KIND = {"affine": 0, "hash": 1}
 
 
+class Weight(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("a", ctypes.c_int32), ("b", ctypes.c_int32), ("seed", ctypes.c_uint32)]
+
+
+class GapDesc(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("w_row", Weight), ("w_col", Weight),
+                ("s_match", ctypes.c_int32), ("s_mismatch", ctypes.c_int32), ("s_bits", ctypes.c_int32),
+                ("s_seed_x", ctypes.c_uint32), ("s_seed_y", ctypes.c_uint32), ("part", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("min_piece", ctypes.c_int32), ("D", ctypes.c_void_p),
+                ("ldd", ctypes.c_int64)]
+
+
+class GapResult(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("launches", ctypes.c_int32), ("base_blocks", ctypes.c_int64),
+                ("cubes", ctypes.c_int64), ("pieces", ctypes.c_int64)]
+
+
+def _weight(w):
+    """(kind, a, b, seed) -> Weight"""
+    return Weight(W_KIND[w[0]], w[1], w[2], w[3] & 0xFFFFFFFF)
+
+
 class StrassenDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
                 ("p", ctypes.c_int32), ("gamma", ctypes.c_int32), ("base", ctypes.c_int64),
@@ -186,6 +208,8 @@ def lib():
     L.paco_peak.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     L.paco_strassen_pbfs.argtypes = [vp, ctypes.POINTER(StrassenDesc), ctypes.POINTER(StrassenResult)]
     L.paco_dp1d.argtypes = [vp, ctypes.POINTER(Dp1dDesc), ctypes.POINTER(Dp1dResult)]
+    L.paco_gap.argtypes = [vp, ctypes.POINTER(GapDesc), ctypes.POINTER(GapResult)]
+    L.paco_gap_plan_export.argtypes = [i64, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
     L.paco_dp1d_plan_export.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         vp, vp, vp]
     L.paco_strassen_schedule.argtypes = [i64, ctypes.c_int32, ctypes.c_int32, i64,
@@ -257,6 +281,23 @@ def dp1d_plan(n, part="paco", p=1024, base=512, min_piece=65536):
     pc = np.zeros((max(int(info[1]), 1), 5), np.int64)
     _check(L.paco_dp1d_plan_export(n, PART[part], p, base, min_piece, vp(info), vp(sq), vp(pc)))
     return int(info[2]), int(info[3]), sq[:int(info[0])], pc[:int(info[1])]
+
+
+def gap_plan(m, n, part="paco", p=1024, min_piece=65536):
+    """Host-only: the plan of paco_gap.  Returns (launches, blocks, pieces,
+    cubes): launches an (L, 3) int64 array (1 base / 0 cubes, first entry,
+    count), blocks (B, 4) (r0, r1, c0, c1), pieces (P, 7) (column-gap flag,
+    t0, t1, x0, x1, o0, o1)."""
+    import numpy as np
+    L = lib()
+    info = np.zeros(4, np.int64)
+    vp = lambda a: ctypes.c_void_p(a.ctypes.data)
+    _check(L.paco_gap_plan_export(m, n, PART[part], p, min_piece, vp(info), None, None, None))
+    la = np.zeros((max(int(info[0]), 1), 3), np.int64)
+    bl = np.zeros((max(int(info[1]), 1), 4), np.int64)
+    pc = np.zeros((max(int(info[2]), 1), 7), np.int64)
+    _check(L.paco_gap_plan_export(m, n, PART[part], p, min_piece, vp(info), vp(la), vp(bl), vp(pc)))
+    return la[:int(info[0])], bl[:int(info[1])], pc[:int(info[2])], int(info[3])
 
 
 def partition(n, m, k, p, q=(1, 1, 1), weights=None, multi_piece=False, kcut_cost=1.0, max_rounds=0):
@@ -528,6 +569,24 @@ class Context:
         _check(self._L.paco_dp1d(self._h, ctypes.byref(d), ctypes.byref(r)), self._h)
         if return_result:
             return D, {f[0]: getattr(r, f[0]) for f in Dp1dResult._fields_}
+        return D
+
+    def gap(self, D, w_row, w_col, s, part="paco", p=0, min_piece=0, return_result=False):
+        """The GAP problem (section "PACO GAP") in place on D, an (m+1) x (n+1)
+        int32 tensor (unit column stride): D[0, 0] is read, every cell is
+        written.  w_row, w_col: (kind, a, b, seed); s: (s_match, s_mismatch,
+        bits, seed_x, seed_y)."""
+        if not isinstance(D, torch.Tensor) or D.device.type != "cuda" or D.device.index != self.device:
+            raise ValueError(f"D must be a tensor on cuda:{self.device}")
+        if D.dtype != torch.int32 or D.dim() != 2 or D.stride(1) != 1 or D.shape[0] < 1 or D.shape[1] < 1:
+            raise ValueError("D must be a 2-D int32 tensor with unit column stride")
+        d = GapDesc(D.shape[0] - 1, D.shape[1] - 1, _weight(w_row), _weight(w_col), s[0], s[1], s[2],
+                    s[3] & 0xFFFFFFFF, s[4] & 0xFFFFFFFF, PART[part], p, min_piece, _ptr(D), D.stride(0))
+        r = GapResult()
+        self._stream()
+        _check(self._L.paco_gap(self._h, ctypes.byref(d), ctypes.byref(r)), self._h)
+        if return_result:
+            return D, {f[0]: getattr(r, f[0]) for f in GapResult._fields_}
         return D
 
     def strassen_pbfs(self, A, B, C=None, p=0, gamma=0, base=0, leaf="bf16x3", return_result=False):

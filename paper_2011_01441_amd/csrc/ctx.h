@@ -45,6 +45,8 @@ struct paco_ctx_s {
   uint64_t ws_bytes = 0;
   void* sws = nullptr;       // Strassen temporaries
   uint64_t sws_bytes = 0;
+  void* gws = nullptr;       // GAP problem: transposed copy of the final values
+  uint64_t gws_bytes = 0;
   double* d_verify = nullptr;  // 4 doubles + row list
   int64_t* d_rows = nullptr;
   int64_t rows_cap = 0;

@@ -97,6 +97,31 @@ hipError_t launch_dp1d_fill(int wk, uint32_t* D, int64_t n, uint32_t* cnt, int t
 hipError_t launch_dp1d_rect(int wk, uint32_t* D, const DpPiece* pieces, int npieces, int ntri, uint32_t* cnt,
                             int64_t tri_lo, int tri_len, const DpW& w, hipStream_t s);
 
+// GAP problem (section "PACO GAP"): a weight function (kind 0 affine with
+// b the slope, kind 1 hashed with b the mask), the substitution cost, a base
+// block and one cube piece
+struct GapW {
+  uint32_t kind, a, b, seed;
+};
+struct GapS {
+  uint32_t match, mismatch, mask, seedx, seedy, pad;
+};
+struct GapBlock {
+  int64_t r0, r1, c0, c1;   // rows [r0, r1) x columns [c0, c1)
+};
+struct GapPiece {
+  int64_t t0, t1;   // batch: rows (row gaps) or columns (column gaps)
+  int64_t x0, x1;   // inputs (columns q, or rows p)
+  int64_t o0, o1;   // outputs (columns j, or rows i)
+  int32_t col, pad; // 1: column-gap piece (inputs read from DT)
+};
+constexpr int GAP_B = 64;   // largest base block side
+hipError_t launch_gap_fill(uint32_t* D, int64_t ld, int64_t rows, int64_t cols, hipStream_t s);
+hipError_t launch_gap_base(uint32_t* D, int64_t ld, uint32_t* DT, int64_t ldt, const GapBlock* blocks, int nblocks,
+                           const GapW& wr, const GapW& wc, const GapS& sub, hipStream_t s);
+hipError_t launch_gap_cube(uint32_t* D, int64_t ld, const uint32_t* DT, int64_t ldt, const GapPiece* pieces,
+                           int npieces, const GapW& wr, const GapW& wc, hipStream_t s);
+
 hipError_t launch_calib(int nwg, int iters, uint64_t* stamps, float* sink, hipStream_t s);
 hipError_t launch_peak_valu_i32(int nwg, int iters, uint32_t* sink, hipStream_t s);
 hipError_t launch_peak_valu_f32(int nwg, int iters, float* sink, hipStream_t s);

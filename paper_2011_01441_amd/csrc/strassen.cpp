@@ -45,6 +45,8 @@ paco_status ensure_sws(paco_ctx ctx, uint64_t bytes) {
 
 namespace paco {
 void destroy_ctx_extras(paco_ctx ctx) {
+  if (ctx->gws) (void)hipFree(ctx->gws);
+  ctx->gws = nullptr;
   if (ctx->sws) (void)hipFree(ctx->sws);
   if (ctx->d_rows) (void)hipFree(ctx->d_rows);
   ctx->sws = nullptr;
