@@ -50,6 +50,14 @@ WORKLOADS = {
     "dp1d_hash": dict(kind="dp1d", n=1 << 20, wk="hash", a=0, b=20, base=512,
                       desc="1D problem (least weight subsequence), n=2^20, w(i,j) = MurmurHash3 "
                            "finaliser of (i, j) mod 2^20"),
+    "gap_hash": dict(kind="gap", n=4096, m=4096, w_row=("hash", 0, 12, 3), w_col=("hash", 2, 10, 4),
+                     s=(0, 5, 2, 7, 8),
+                     desc="GAP problem (edit distance with gaps), 4097x4097 grid, hashed gap weights "
+                          "(12 and 10 bits), 4-symbol hashed sequences, match 0 / mismatch 5"),
+    "gap_affine": dict(kind="gap", n=4096, m=4096, w_row=("affine", 4, 1, 0), w_col=("affine", 4, 1, 0),
+                       s=(0, 3, 2, 7, 8),
+                       desc="GAP problem with affine gap costs 4 + k (Gotoh's case), 4097x4097 grid, "
+                            "4-symbol hashed sequences, match 0 / mismatch 3"),
     "strassen_c3_levels2": dict(kind="strassen", n=16384, mode="levels", levels=2, prec="bf16x3",
                                 desc="Strassen 2 fixed levels, 49 leaves as one MM-1-Piece batch, "
                                      "n=16384 f32 U[-1,1], bf16x3 leaf"),
@@ -101,6 +109,9 @@ def make_inputs(w, torch, dev):
         # D[0] = 0; D[1..n] are outputs (the weights need no memory)
         A = np.zeros(w["n"] + 1, np.int32)
         B = np.zeros(1, np.int32)
+    elif kind == "gap":
+        A = np.zeros((w["m"] + 1, w["n"] + 1), np.int32)
+        B = np.zeros(1, np.int32)
     log(f"inputs generated in {time.time() - t0:.1f}s")
     return A, B, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
 
@@ -126,6 +137,16 @@ def algorithmic(w, prec):
     if kind in ("minplus", "maxplus"):
         # two adds and one min3/max3 per two l
         return 1.5 * w["n"] * w["m"] * w["k"], "T lane-instr/s", "alu", PEAK["valu"]
+    if kind == "gap":
+        # the cube kernel's pairs (every row pair q < j and column pair p < i
+        # outside the base blocks), at the 1D problem's slots per pair
+        import paper_2011_01441_amd as P
+        m, n = w["m"], w["n"]
+        _, bl, _, _ = P.gap_plan(m, n, "paco", 1024, 65536)
+        inblock = int(sum((r1 - r0) * (c1 - c0) * ((c1 - c0 - 1) + (r1 - r0 - 1)) // 2 for r0, r1, c0, c1 in bl))
+        pairs = (m + 1) * n * (n + 1) / 2 + (n + 1) * m * (m + 1) / 2 - inblock
+        per = 15.5 if w["w_row"][0] == "hash" else 1.5
+        return per * pairs, "T lane-instr/s", "alu", PEAK["valu"]
     if kind == "dp1d":
         # per pair (i < j): affine weights fold into one add and half a
         # min3, as (min,+); hashed weights add the key (add, xor with the
@@ -146,11 +167,22 @@ def classic_ops(w):
         return 2.0 * w["n"] ** 3
     if w["kind"] == "dp1d":   # one add and one min per pair i < j
         return float(w["n"]) * (w["n"] + 1)
+    if w["kind"] == "gap":    # one add and one min per row pair, column pair and diagonal term
+        m, n = w["m"], w["n"]
+        return 2.0 * ((m + 1) * n * (n + 1) / 2 + (n + 1) * m * (m + 1) / 2 + m * n)
     return 2.0 * w["n"] * w["m"] * w["k"]
 
 
 def call(ctx, w, Ad, Bd, C, **kw):
     kind = w["kind"]
+    if kind == "gap":
+        part = kw.pop("part", "paco")
+        kw.pop("split_k", None)
+        rr = kw.pop("return_result", False)
+        r = ctx.gap(Ad, w["w_row"], w["w_col"], w["s"], part=part, return_result=rr)
+        if rr:
+            r[1]["n_pieces"], r[1]["n_kcuts"], r[1]["kcut_cost"] = r[1]["pieces"], 0, None
+        return r
     if kind == "dp1d":
         part = kw.pop("part", "paco")
         kw.pop("split_k", None)
@@ -185,6 +217,21 @@ def cpu_baseline(w, A, B, target_s):
     thr = oracle.num_threads()
     kind = w["kind"]
     n = w["n"]
+    if kind == "gap":
+        # the grid fills in row-major order: the sample is a square m_s x m_s
+        # top-left part of the same instance
+        ms = 256
+        while True:
+            t0 = time.perf_counter()
+            oracle.gap(ms, ms, w["w_row"], w["w_col"], w["s"])
+            dt = time.perf_counter() - t0
+            if dt >= target_s / 2 or ms >= n:
+                break
+            ms = min(n, int(ms * max(1.2, (1.1 * target_s / max(dt, 1e-3)) ** (1 / 3))))
+        ops = 2.0 * ((ms + 1) * ms * (ms + 1) / 2 * 2 + ms * ms)
+        return {"value": ops / dt / 1e9, "unit": "GOP/s", "cores": 1, "kind": "oracle",
+                "sample": f"the top-left {ms + 1}x{ms + 1} part of the same instance, {dt:.1f} s",
+                "seconds": dt}
     if kind == "dp1d":
         # the recurrence is sequential in j: the sample is a prefix n_s of
         # the same instance (work n_s (n_s + 1) / 2 pairs)
@@ -343,7 +390,7 @@ def main():
         C = torch.empty((w["n"], (w["m"] + 31) // 32), dtype=torch.int32, device=dev)
     elif w["kind"] == "strassen":
         C = torch.empty((w["n"], w["n"]), dtype=torch.float32, device=dev)
-    elif w["kind"] == "dp1d":
+    elif w["kind"] in ("dp1d", "gap"):
         C = None
     else:
         C = torch.empty((w["n"], w["m"]), dtype=Ad.dtype, device=dev)
@@ -396,7 +443,7 @@ def main():
     ctx.timing(False)
     # per launch of the dominant kernel; the 1D problem launches its square
     # kernel once per square, so there the unit is one call (all of them)
-    per = args.steps if w["kind"] == "dp1d" else max(tm["launches"], 1)
+    per = args.steps if w["kind"] in ("dp1d", "gap") else max(tm["launches"], 1)
     kern_ms = tm["main_ms"] / per
     red_ms = tm["reduce_ms"] / per
     other_ms = tm["other_ms"] / per
@@ -413,7 +460,7 @@ def main():
 
     # ---- the same step captured once into a hipGraph and replayed
     graph = None
-    if not args.no_graph and w["kind"] != "dp1d" and not (w["kind"] == "strassen" and w["mode"] != "pbfs"):
+    if not args.no_graph and w["kind"] not in ("dp1d", "gap") and not (w["kind"] == "strassen" and w["mode"] != "pbfs"):
         # one graph holds `steps` back-to-back steps (a graph launch has a
         # fixed cost of its own); it is replayed twice untimed, then timed once
         rep = args.steps
@@ -446,13 +493,15 @@ def main():
 
     # ---- plain tile grid (same microkernels), tile shape and split-k autotuned
     grid = None
-    if not args.no_grid and w["kind"] == "dp1d":
-        # outputs-only strips (no input cuts), same kernels and base triangles
+    if not args.no_grid and w["kind"] in ("dp1d", "gap"):
+        # 1D: outputs-only strips (no input cuts); GAP: a fixed tile grid of
+        # every cube; same kernels and base cases
         f = lambda: call(ctx, w, Ad, Bd, C, part="grid")
         f()
         gms = timed(torch, f, args.steps) * 1e3
         grid = {"value": classic_ops(w) / (gms * 1e-3) / 1e9, "ms_per_step": round(gms, 4),
-                "tile": None, "split_k": None, "partition": "output strips only"}
+                "tile": None, "split_k": None,
+                "partition": "output strips only" if w["kind"] == "dp1d" else "16 x 256 cube tiles"}
         log(f"grid: {gms:.3f} ms/step")
     elif not args.no_grid and w["kind"] != "strassen":
         tile_env = {"ring": "PACO_RING_TILE", "bool": "PACO_BOOL_TILE"}.get(w["kind"], "PACO_INT_TILE")
@@ -476,6 +525,15 @@ def main():
 
     # ---- accuracy of this result
     err = None
+    if w["kind"] == "gap":
+        import oracle
+        call(ctx, w, Ad, Bd, C)
+        Dh = Ad.cpu().numpy()
+        rng = np.random.default_rng(0)
+        cells = np.concatenate([rng.integers(0, w["m"] + 1, (256, 2)), [[w["m"], w["n"]], [0, w["n"]], [w["m"], 0]]])
+        bad = oracle.gap_check(Dh, cells, w["w_row"], w["w_col"], w["s"])
+        err = {"sampled_cells": int(cells.shape[0]), "mismatches": int(bad),
+               "check": "each sampled cell equals the recurrence over the GPU's own grid"}
     if w["kind"] == "dp1d":
         import oracle
         call(ctx, w, Ad, Bd, C)
@@ -524,11 +582,13 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"ring": "bf16" if prec != "fp32" else "f32", "strassen": "bf16",
-                  "minplus": "u32", "maxplus": "i32", "bool": "u32", "dp1d": "u32"}[w["kind"]],
+                  "minplus": "u32", "maxplus": "i32", "bool": "u32", "dp1d": "u32", "gap": "u32"}[w["kind"]],
         "data": "synthetic",
         "config": {"workload": args.workload, "desc": w["desc"], "precision": prec,
                    "partition": ("PACO 1D: squares cut by the MM-1-Piece rule, base triangles of %d"
-                                 % w["base"]) if w["kind"] == "dp1d" else "PACO MM-1-Piece",
+                                 % w["base"]) if w["kind"] == "dp1d" else
+                                ("PACO GAP: cubes in batch slabs, 64 x 64 base blocks" if w["kind"] == "gap"
+                                 else "PACO MM-1-Piece"),
                    "p": res["p"] if res else None,
                    "kcut_cost": res["kcut_cost"] if res else None,
                    "processor_weights": ("measured per-XCD matrix-core rates, max/min %.4f" %
@@ -536,11 +596,15 @@ def main():
                    "pieces": res["n_pieces"] if res else None,
                    "kcut_faces": res["n_kcuts"] if res else None,
                    "parallelism": "one GPU, 256 CUs"},
-        "roofline": {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+        "roofline": {"kernel": {"ring": "k_ring", "strassen": "k_ring", "minplus": "k_semiring_int",
+                                "maxplus": "k_semiring_int", "bool": "k_semiring_bool",
+                                "dp1d": "k_dp1d_rect (with the base triangles it runs), all launches of a call",
+                                "gap": "k_gap_cube, all launches of a call (reduce_ms: k_gap_base)"}[w["kind"]],
+                     "bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                      "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.workload),
                      "kernel_ms": round(kern_ms, 4), "reduce_ms": round(red_ms, 4),
                      "other_ms": round(other_ms, 4), "work_per_launch": work,
-                     "launches_per_unit": (tm["launches"] // args.steps) if w["kind"] == "dp1d" else 1},
+                     "launches_per_unit": (tm["launches"] // args.steps) if w["kind"] in ("dp1d", "gap") else 1},
         "single_call": call_stats,
         "measured_peaks": peaks,
         "grid_baseline": grid,
