@@ -57,9 +57,10 @@ __device__ __forceinline__ uint32_t load_dev(const uint32_t* p) {
 //  2. wave 0 walks the chain: output t is final once every earlier output of
 //     the block has been applied to it, so lane t's value is read as a
 //     wave-uniform scalar and applied to the lanes after it;
-//  3. every wave takes the finished block into one register (lane t holds
-//     input blk + t) and applies it to its 64-output strips of the rest of
-//     the triangle, broadcasting input t with a lane read.
+//  3. every wave takes a quarter of the finished block's inputs (read out
+//     of one register by lane reads, once per block) and applies them to
+//     every later output of the triangle; the waves' minima meet by LDS
+//     atomic minima.
 template <int WK>
 __device__ void tri_body(uint32_t* __restrict__ D, int64_t lo, int len, const DpW& w, uint32_t* d,
                          uint32_t* wl) {
@@ -106,23 +107,26 @@ __device__ void tri_body(uint32_t* __restrict__ D, int64_t lo, int len, const Dp
       // lane t: input blk + t; affine weights fold their input-only part
       // -b i into it, so D[i] + w(i, j) = vin_t + (a + b j)
       const uint32_t vin = WK == 0 ? d[blk + lane] - w.b * (i0 + (uint32_t)lane) : d[blk + lane];
+      // wave v applies inputs blk + 16 v .. blk + 16 v + 15 to every later
+      // output; the four waves' minima meet in LDS (atomic minimum)
+      const int t0 = 16 * __builtin_amdgcn_readfirstlane(wv);
+      uint32_t sv[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) sv[k] = (uint32_t)__builtin_amdgcn_readlane((int)vin, t0 + k);
 #pragma unroll 1
-      for (int o0 = blk + 64 + 64 * wv; o0 < len; o0 += 256) {
+      for (int o0 = blk + 64; o0 < len; o0 += 64) {
         const int o = o0 + lane;
         const uint32_t j = (uint32_t)(lo + o);
-        uint32_t acc = o < len ? d[o] : DP_INF;
+        uint32_t acc = DP_INF;
         if constexpr (WK == 0) {
           const uint32_t cj = w.a + w.b * j;
-#pragma unroll 16
-          for (int t = 0; t < 64; ++t) acc = umin(acc, (uint32_t)__builtin_amdgcn_readlane((int)vin, t) + cj);
+#pragma unroll
+          for (int k = 0; k < 16; ++k) acc = umin(acc, sv[k] + cj);
         } else {
-#pragma unroll 16
-          for (int t = 0; t < 64; ++t) {
-            const uint32_t dt = (uint32_t)__builtin_amdgcn_readlane((int)vin, t);
-            acc = umin(acc, dt + wval<WK>(w, i0 + t, j));
-          }
+#pragma unroll
+          for (int k = 0; k < 16; ++k) acc = umin(acc, sv[k] + wval<WK>(w, i0 + (uint32_t)(t0 + k), j));
         }
-        if (o < len) d[o] = umin(acc, DP_INF);
+        if (o < len) atomicMin(d + o, acc);
       }
     }
     // the next block's weight pass touches only wl, which nothing reads now
