@@ -145,16 +145,17 @@ def algorithmic(w, prec):
         _, bl, _, _ = P.gap_plan(m, n, "paco", 1024, 65536)
         inblock = int(sum((r1 - r0) * (c1 - c0) * ((c1 - c0 - 1) + (r1 - r0 - 1)) // 2 for r0, r1, c0, c1 in bl))
         pairs = (m + 1) * n * (n + 1) / 2 + (n + 1) * m * (m + 1) / 2 - inblock
-        per = 15.5 if w["w_row"][0] == "hash" else 1.5
+        per = 9.5 if w["w_row"][0] == "hash" else 1.5
         return per * pairs, "T lane-instr/s", "alu", PEAK["valu"]
     if kind == "dp1d":
         # per pair (i < j): affine weights fold into one add and half a
         # min3, as (min,+); hashed weights add the key (add, xor with the
-        # seed), the finaliser (two 16-bit shift-xors, one word-select form
-        # each; a shift and an xor; two multiplies at a quarter of the issue
-        # rate, 4 slots each), the mask and the add of D[i]: 15.5 slots
+        # seed), the finaliser (two 16-bit shift-xors, one word-select xor
+        # each; a shift and an xor; two multiplies, full rate on this part),
+        # the mask (fused into a three-input bit operation), the add of D[i]
+        # and half a min3: 9.5 instructions
         pairs = w["n"] * (w["n"] + 1) / 2
-        per = 1.5 if w["wk"] == "affine" else 15.5
+        per = 1.5 if w["wk"] == "affine" else 9.5
         return per * pairs, "T lane-instr/s", "alu", PEAK["valu"]
     if kind == "bool":
         # one and-or per (row, bit of k, word of the output row)
