@@ -142,7 +142,7 @@ def algorithmic(w, prec):
         # outside the base blocks), at the 1D problem's slots per pair
         import paper_2011_01441_amd as P
         m, n = w["m"], w["n"]
-        _, bl, _, _ = P.gap_plan(m, n, "paco", 1024, 65536)
+        _, bl, _, _ = P.gap_plan(m, n, "paco", 1024, 16384)
         inblock = int(sum((r1 - r0) * (c1 - c0) * ((c1 - c0 - 1) + (r1 - r0 - 1)) // 2 for r0, r1, c0, c1 in bl))
         pairs = (m + 1) * n * (n + 1) / 2 + (n + 1) * m * (m + 1) / 2 - inblock
         per = 9.5 if w["w_row"][0] == "hash" else 1.5

@@ -377,7 +377,7 @@ typedef struct paco_gap_desc {
   uint32_t s_seed_x, s_seed_y;
   int32_t part;              /* PACO_PART_PACO or PACO_PART_GRID */
   int32_t p;                 /* processors; 0: 4 per compute unit */
-  int32_t min_piece;         /* least pairs per piece; 0: 65536 */
+  int32_t min_piece;         /* least pairs per piece; 0: 16384 */
   int32_t* D;
   int64_t ldd;               /* >= n + 1 */
 } paco_gap_desc;

@@ -212,7 +212,7 @@ extern "C" paco_status paco_gap(paco_ctx ctx, const paco_gap_desc* d, paco_gap_r
            (uint32_t)(d->s_bits >= 32 ? 0xFFFFFFFFull : (((uint64_t)1 << d->s_bits) - 1)), d->s_seed_x,
            d->s_seed_y, 0u};
   const int p = d->p > 0 ? d->p : 4 * ctx->num_cus;
-  const int64_t min_piece = d->min_piece > 0 ? d->min_piece : 65536;
+  const int64_t min_piece = d->min_piece > 0 ? d->min_piece : 16384;
   if (res) memset(res, 0, sizeof *res);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");

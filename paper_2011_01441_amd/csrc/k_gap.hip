@@ -167,17 +167,18 @@ __global__ __launch_bounds__(GAP_THREADS) void k_gap_base(uint32_t* __restrict__
 // t in [t0, t1), D[t][o] = min over inputs x in [x0, x1) of D[t][x] + w(x, o),
 // outputs o in [o0, o1).  Column-gap piece (col = 1): for columns t,
 // D[o][t] = min over x of DT[t][x] + w'(x, o).  A wave takes one batch index,
-// four 64-output strips (four outputs per lane) and a slice of the inputs,
-// read 8 at a time as wave-uniform values.
+// four 64-output strips (four outputs per lane; one strip when the piece is
+// at most 128 outputs wide) and a slice of the inputs, read 8 at a time as
+// wave-uniform values.
 constexpr int GR = 4;
 
-template <int WK>
+template <int WK, int NR>
 __device__ __forceinline__ void cube_unit(uint32_t* __restrict__ D, int64_t ld, const uint32_t* __restrict__ src,
                                           bool col, int64_t t, int64_t ob, int64_t o1, int64_t xa, int64_t xb,
                                           const GapW& w) {
-  uint32_t ou[GR], acc[GR];
+  uint32_t ou[NR], acc[NR];
 #pragma unroll
-  for (int r = 0; r < GR; ++r) {
+  for (int r = 0; r < NR; ++r) {
     ou[r] = (uint32_t)(ob + 64 * r);
     acc[r] = G_INF;
   }
@@ -189,16 +190,16 @@ __device__ __forceinline__ void cube_unit(uint32_t* __restrict__ D, int64_t ld, 
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
 #pragma unroll
-      for (int r = 0; r < GR; ++r) acc[r] = gmin(acc[r], dv[k] + gw<WK>(w, (uint32_t)(x + k), ou[r]));
+      for (int r = 0; r < NR; ++r) acc[r] = gmin(acc[r], dv[k] + gw<WK>(w, (uint32_t)(x + k), ou[r]));
     }
   }
   for (; x < xb; ++x) {
     const uint32_t dx = src[x];
 #pragma unroll
-    for (int r = 0; r < GR; ++r) acc[r] = gmin(acc[r], dx + gw<WK>(w, (uint32_t)x, ou[r]));
+    for (int r = 0; r < NR; ++r) acc[r] = gmin(acc[r], dx + gw<WK>(w, (uint32_t)x, ou[r]));
   }
 #pragma unroll
-  for (int r = 0; r < GR; ++r) {
+  for (int r = 0; r < NR; ++r) {
     const int64_t o = ob + 64 * r;
     if (o < o1) atomicMin(col ? D + o * ld + t : D + t * ld + o, gmin(acc[r], G_INF));
   }
@@ -213,7 +214,9 @@ __global__ __launch_bounds__(256) void k_gap_cube(uint32_t* __restrict__ D, int6
   if (T <= 0 || W <= 0 || H <= 0) return;
   const bool col = pc.col != 0;
   const GapW w = col ? wc : wr;
-  const int64_t groups = (W + 64 * GR - 1) / (64 * GR);
+  // narrow pieces (at most two strips) take one 64-output strip per unit
+  const int nr = W <= 128 ? 1 : GR;
+  const int64_t groups = (W + 64 * nr - 1) / (64 * nr);
   const int S = T * groups >= 4 ? 1 : (T * groups >= 2 ? 2 : 4);
   const int64_t units = T * groups * S;
   for (int64_t un = wv; un < units; un += 4) {
@@ -221,13 +224,19 @@ __global__ __launch_bounds__(256) void k_gap_cube(uint32_t* __restrict__ D, int6
     const int64_t rest = un / S;
     const int64_t t = pc.t0 + rest / groups;
     const int64_t g = rest % groups;
-    const int64_t ob = pc.o0 + g * 64 * GR + lane;
+    const int64_t ob = pc.o0 + g * 64 * nr + lane;
     const int64_t xa = pc.x0 + H * slice / S, xb = pc.x0 + H * (slice + 1) / S;
     const uint32_t* src = col ? DT + t * ldt : D + t * ld;
-    if (w.kind == 0) {
-      cube_unit<0>(D, ld, src, col, t, ob, pc.o1, xa, xb, w);
+    if (nr == 1) {
+      if (w.kind == 0) {
+        cube_unit<0, 1>(D, ld, src, col, t, ob, pc.o1, xa, xb, w);
+      } else {
+        cube_unit<1, 1>(D, ld, src, col, t, ob, pc.o1, xa, xb, w);
+      }
+    } else if (w.kind == 0) {
+      cube_unit<0, GR>(D, ld, src, col, t, ob, pc.o1, xa, xb, w);
     } else {
-      cube_unit<1>(D, ld, src, col, t, ob, pc.o1, xa, xb, w);
+      cube_unit<1, GR>(D, ld, src, col, t, ob, pc.o1, xa, xb, w);
     }
   }
 }
