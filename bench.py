@@ -212,7 +212,37 @@ def timed(torch, fn, steps):
     return (time.perf_counter() - t0) / steps
 
 
+def host_info():
+    """CPU model and the cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(w, A, B, target_s):
+    """The oracle on all its threads, then on one, each on a bounded sample
+    of the same inputs."""
+    import oracle
+    full = cpu_sample(w, A, B, target_s)
+    thr = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        one = cpu_sample(w, A, B, max(2.0, target_s / 4))
+    finally:
+        oracle.set_threads(thr)
+    full["single_thread"] = {"value": one["value"], "sample": one["sample"], "seconds": one["seconds"]}
+    full["host"] = host_info()
+    return full
+
+
+def cpu_sample(w, A, B, target_s):
     """The oracle as it stands, on a bounded row sample of the same inputs."""
     import oracle
     thr = oracle.num_threads()

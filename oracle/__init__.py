@@ -39,6 +39,7 @@ def lib():
         L.oracle_ring_i64.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64]
         L.oracle_strassen_f64.argtypes = [i64, vp, vp, vp, ci]
         L.oracle_strassen_i64.argtypes = [i64, vp, vp, vp, ci]
+        L.oracle_set_threads.argtypes = [ci]
         L.oracle_fmix32.argtypes = [ctypes.c_uint32]
         L.oracle_fmix32.restype = ctypes.c_uint32
         L.oracle_dp1d_w.argtypes = [ci, i64, i64, ctypes.c_uint32, i64, i64]
@@ -235,3 +236,8 @@ def unpack_bits(W, cols):
 
 def num_threads():
     return lib().oracle_num_threads()
+
+
+def set_threads(n):
+    """Threads for the oracle's OpenMP loops from now on."""
+    lib().oracle_set_threads(int(n))

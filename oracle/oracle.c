@@ -403,6 +403,15 @@ int64_t oracle_gap_check(int64_t m, int64_t n, const int64_t* wr, const int64_t*
   return bad;
 }
 
+/* Threads for the OpenMP loops that follow (no effect without OpenMP). */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* Threads an OpenMP loop of this library runs on (1 without OpenMP). */
 int oracle_num_threads(void) {
 #ifdef _OPENMP
