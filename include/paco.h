@@ -108,7 +108,11 @@ typedef struct paco_ctx_s* paco_ctx;
 /* Create a context on HIP device `device`.  workspace_budget_bytes caps the
  * device workspace the context may hold (0 = 64 GiB).  The context creates
  * no stream of its own; it launches on the stream set by paco_set_stream
- * (initially the null stream). */
+ * (initially the null stream).  It caches one plan (host work lists and
+ * their device tables) per call shape, up to 512: a call that needs a new
+ * plan when 512 are held first synchronises the device and drops them all,
+ * after which graphs captured earlier refuse to replay (PACO_ERR_INVALID_ARG
+ * from paco_graph_launch, as after a workspace change). */
 paco_status paco_create(paco_ctx* out, int device, uint64_t workspace_budget_bytes);
 paco_status paco_destroy(paco_ctx ctx);
 /* `stream` is a hipStream_t passed as an opaque pointer. */

@@ -115,6 +115,15 @@ static hipEvent_t take_event(paco_ctx ctx) {
   return e;
 }
 
+void trim_plans(paco_ctx ctx) {
+  if (ctx->plans.size() < PACO_PLAN_CACHE_MAX) return;
+  // kernels in flight, on whichever stream the calls used, may still read
+  // the plans' device tables
+  (void)hipDeviceSynchronize();
+  ctx->plans.clear();
+  ctx->ws_gen += 1;   // captured graphs that point into them refuse to replay
+}
+
 TimeScope::TimeScope(paco_ctx c, int r) : ctx(c), role(r) {
   if (!ctx->timing) return;
   a = take_event(ctx);
@@ -671,6 +680,7 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
   if (itp != ctx->plans.end()) {
     dp = itp->second.get();
   } else {
+    trim_plans(ctx);
     std::unique_ptr<DevPlan> np(new DevPlan());
     make_mm_plan((int)d->sr, z.n, z.m, z.k, part, p, d->grid_split_k, z.prec, ctx->num_cus, np.get(), kc, weights,
                  force_tile);

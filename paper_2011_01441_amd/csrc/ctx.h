@@ -65,6 +65,9 @@ struct paco_ctx_s {
 
 namespace paco {
 
+// plans a context keeps before it synchronises the device and starts over
+constexpr size_t PACO_PLAN_CACHE_MAX = 512;
+void trim_plans(paco_ctx ctx);
 void set_err(paco_ctx ctx, const std::string& msg);
 paco_status hip_fail(paco_ctx ctx, hipError_t e, const char* what);
 paco_status upload_plan(paco_ctx ctx, DevPlan* dp);

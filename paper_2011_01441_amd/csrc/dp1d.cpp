@@ -169,6 +169,7 @@ extern "C" paco_status paco_dp1d(paco_ctx ctx, const paco_dp1d_desc* d, paco_dp1
   if (it != ctx->plans.end()) {
     pl = static_cast<Dp1dPlan*>(it->second.get());
   } else {
+    trim_plans(ctx);
     std::unique_ptr<Dp1dPlan> np(new Dp1dPlan());
     Builder b{np.get(), d->part, p, base, min_piece};
     b.rec(0, d->n + 1);

@@ -229,6 +229,7 @@ extern "C" paco_status paco_gap(paco_ctx ctx, const paco_gap_desc* d, paco_gap_r
   if (it != ctx->plans.end()) {
     pl = static_cast<GapPlan*>(it->second.get());
   } else {
+    trim_plans(ctx);
     std::unique_ptr<GapPlan> np(new GapPlan());
     build_gap_plan(np.get(), d->m, d->n, d->part, p, min_piece);
     if (!np->blocks.empty() && (e = hipMalloc(&np->d_blocks, sizeof(GapBlock) * np->blocks.size())) != hipSuccess)

@@ -94,7 +94,7 @@ extern "C" paco_status paco_graph_create_strassen(paco_ctx ctx, const paco_stras
 extern "C" paco_status paco_graph_launch(paco_graph g, void* stream) {
   if (!g) return PACO_ERR_INVALID_ARG;
   if (g->ws_gen != g->ctx->ws_gen) {   // the workspace it points into was replaced
-    set_err(g->ctx, "graph is stale: the context workspace was reallocated after capture");
+    set_err(g->ctx, "graph is stale: the context workspace or plans were replaced after capture");
     return PACO_ERR_INVALID_ARG;
   }
   hipError_t e = hipGraphLaunch(g->ge, stream ? (hipStream_t)stream : g->ctx->stream);

@@ -99,6 +99,7 @@ extern "C" paco_status paco_strassen_mm(paco_ctx ctx, int64_t n, const float* A,
   if (itp != ctx->plans.end()) {
     dp = itp->second.get();
   } else {
+    trim_plans(ctx);
     std::unique_ptr<DevPlan> np(new DevPlan());
     PartOpts po;
     po.p = p;
@@ -308,6 +309,7 @@ extern "C" paco_status paco_strassen_pbfs(paco_ctx ctx, const paco_strassen_desc
   if (itp != ctx->plans.end()) {
     sp = static_cast<SPlan*>(itp->second.get());
   } else {
+    trim_plans(ctx);
     std::unique_ptr<SPlan> np(new SPlan());
     np->sched = sched;
     np->first = first;

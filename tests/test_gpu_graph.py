@@ -110,6 +110,32 @@ def test_stale_graph_is_refused():
         c.close()
 
 
+def test_plan_cache_is_bounded():
+    # 520 call shapes overflow the 512-plan cache: every result stays exact,
+    # and a graph captured before the cache was dropped refuses to replay
+    print("case: plan cache bound", flush=True)
+    c = P.Context(0)
+    try:
+        A, B = workloads.minplus_operands(40, 24, 16, seed=26)
+        Cg = torch.empty((40, 24), dtype=torch.int32, device=DEV)
+        g = c.graph(dev(A), dev(B), "minplus", C=Cg)
+        g.launch()
+        assert np.array_equal(host(Cg), oracle.minplus(A, B))
+        Bd = dev(B)
+        for n in range(1, 521):
+            An = dev(A[:n % 40 + 1]) if n <= 40 else dev(np.resize(A, (n, 16)).astype(np.int32))
+            C = c.semiring_mm(An, Bd, "minplus")
+            if n % 97 == 0 or n == 520:
+                assert np.array_equal(host(C), oracle.minplus(host(An), B))
+        with pytest.raises(Exception):
+            g.launch()
+        g.close()
+        C = c.semiring_mm(dev(A), Bd, "minplus")
+        assert np.array_equal(host(C), oracle.minplus(A, B))
+    finally:
+        c.close()
+
+
 # ------------------------------------------------------------ autotuner
 
 @pytest.mark.parametrize("sr", ["minplus", "ring"])
