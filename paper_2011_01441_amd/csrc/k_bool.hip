@@ -19,13 +19,13 @@ constexpr int kThreads = 256;
 constexpr int kBKB = 64;            // bits per step
 constexpr int kKW = kBKB / 32;      // A words per row per step
 
-// All ones if bit l of w is set, else 0 (sign-extended one-bit field).
+// All ones if bit l of w is set, else 0 (sign-extended one-bit field,
+// one v_bfe_i32).
 __device__ __forceinline__ uint32_t bit_mask(uint32_t w, int l) {
-  uint32_t r;
-  asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(w), "v"(l));
-  return r;
+  return (uint32_t)__builtin_amdgcn_sbfe((int)w, l, 1);
 }
-// (a & b) | c in one VALU instruction.
+// (a & b) | c in one VALU instruction (plain C becomes an and plus a shared
+// three-input or, 1.5 instructions).
 __device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t b, uint32_t c) {
   uint32_t r;
   asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
