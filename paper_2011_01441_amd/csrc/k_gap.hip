@@ -65,43 +65,81 @@ __global__ __launch_bounds__(256) void k_gap_fill(uint32_t* __restrict__ D, int6
 // R, C <= GAP_B, whose cells already hold every update from outside the
 // block.  LDS holds the block twice, row-major (hr) and column-major (hc),
 // each with a one-cell halo (the row above and the column to the left,
-// final already, for the diagonal term); hashed weights also get tables
-// (wrt[j][q] = w(q, j), wct[i][p] = w'(p, i)), affine ones are stepped in
-// registers.  Anti-diagonal dd holds the cells with local row + column = dd;
+// final already, for the diagonal term) and padded with INF to GAP_B + 1
+// cells a side; two weight tables (wrt[j][q] = w(q, j), wct[i][p] = w'(p, i))
+// hold GAP_NOPE where the source is not before the target, so that a
+// candidate from outside the cell's predecessors can never win and the
+// candidate reads need no bounds test; the two sequences' symbols sit in
+// sx / sy.  Anti-diagonal dd holds the cells with local row + column = dd;
 // each is final once the diagonals before it are.  GAP_TPC threads per cell
-// take every GAP_TPC-th row and column predecessor; the
-// group's minimum joins the cell's own value and diagonal term.  Rows are
-// GAP_LS words apart (GAP_TPC mod 64 banks): the 64 lanes of a wave read 64
-// different banks.
-constexpr int GAP_TPC = 16;   // threads per cell (measured: 16 beats 8 and 4)
+// take every GAP_TPC-th row and column predecessor, as many slots as the
+// diagonal's longest row or column needs (a block-uniform count, so the
+// reads are issued together); the group's minimum joins the cell's own
+// value and diagonal term.  Waves that hold no cell of the diagonal go
+// straight to the barrier.  Rows are GAP_LS words apart (GAP_TPC mod 64
+// banks): the 64 lanes of a wave read 64 different banks.
+constexpr int GAP_TPC = 16;   // threads per cell (4, 8 or 16; measured: 16 is fastest)
+static_assert(GAP_TPC == 4 || GAP_TPC == 8 || GAP_TPC == 16, "lane groups of 4, 8 or 16");
 constexpr int GAP_THREADS = GAP_B * GAP_TPC;
-constexpr int GAP_LS = 80;    // LDS row stride in words (16 mod 64 banks)
+constexpr int GAP_WAVES = GAP_THREADS / 64;
+constexpr int GAP_CPW = 64 / GAP_TPC;   // cells per wave
+constexpr int GAP_LS = GAP_B + GAP_TPC;   // LDS row stride in words (GAP_TPC mod 64 banks)
+constexpr int GAP_HROWS = (GAP_B + 1 + GAP_WAVES - 1) / GAP_WAVES;   // halo rows per wave
+// weight-table entry of a source at or after the target: values are at most
+// INF = 2^30, so value + GAP_NOPE > INF and stays below 2^32
+constexpr uint32_t GAP_NOPE = 1u << 31;
 
-// minimum over each row of 16 lanes
-__device__ __forceinline__ uint32_t min16(uint32_t v) {
+// minimum over each aligned group of GAP_TPC lanes (every lane of the group
+// gets it): quad swaps, then the other quad of each half-row (mirror), then
+// the other half of each row (rotate by 8)
+__device__ __forceinline__ uint32_t min_group(uint32_t v) {
   v = gmin(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
   v = gmin(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
-  v = gmin(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false));   // row_ror:4
-  v = gmin(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false));   // row_ror:8
+  if constexpr (GAP_TPC >= 8)
+    v = gmin(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  if constexpr (GAP_TPC >= 16)
+    v = gmin(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false));  // row_ror:8
   return v;
 }
 
-// a cell's partial minimum over its row (q = u, u + 4, ... < lj) or column
-// predecessors; `val` the row (or column) in LDS, `wt` the weight table row
-// (hashed) or, affine, weight w0 at the first slot and step down by step
-// (all slots read, indices inside the arrays, so that the reads are in
-// flight together; slots at or past lim are discarded)
-template <int WK>
-__device__ __forceinline__ uint32_t scan_slots(uint32_t acc, const uint32_t* val, const uint32_t* wt, int u, int lim,
-                                               uint32_t w0, uint32_t step) {
+// a cell's minimum: its own value, its diagonal term (the value up-left
+// plus the substitution cost), N slots of its row predecessors (values vr,
+// weights wr_) and N of its column predecessors (vc, wc_), slot k at
+// GAP_TPC k; every read is issued before the first sum
+template <int N>
+__device__ __forceinline__ uint32_t cell_min(const uint32_t* own, const uint32_t* dg, const uint32_t* xs,
+                                             const uint32_t* ys, uint32_t match, uint32_t mismatch,
+                                             const uint32_t* vr, const uint32_t* wr_, const uint32_t* vc,
+                                             const uint32_t* wc_) {
+  uint32_t v[2 * N + 1], w[2 * N + 1];
+  const uint32_t acc0 = *own, sxv = *xs, syv = *ys;
+  v[2 * N] = *dg;
 #pragma unroll
-  for (int k = 0; k < GAP_B / GAP_TPC; ++k) {
-    const int q = u + GAP_TPC * k;
-    const uint32_t wq = WK == 0 ? w0 - step * (uint32_t)k : wt[q];
-    const uint32_t c = val[q] + wq;
-    acc = q < lim ? gmin(acc, c) : acc;
+  for (int k = 0; k < N; ++k) {
+    v[k] = vr[GAP_TPC * k];
+    w[k] = wr_[GAP_TPC * k];
+    v[N + k] = vc[GAP_TPC * k];
+    w[N + k] = wc_[GAP_TPC * k];
   }
+  w[2 * N] = sxv == syv ? match : mismatch;
+  uint32_t acc = acc0;
+#pragma unroll
+  for (int k = 0; k < 2 * N + 1; ++k) acc = gmin(acc, v[k] + w[k]);
   return acc;
+}
+
+// cell_min with the slot count n (block-uniform, 0..N) as a template argument
+template <int N>
+__device__ __forceinline__ uint32_t cell_min_n(int n, const uint32_t* own, const uint32_t* dg, const uint32_t* xs,
+                                               const uint32_t* ys, uint32_t match, uint32_t mismatch,
+                                               const uint32_t* vr, const uint32_t* wr_, const uint32_t* vc,
+                                               const uint32_t* wc_) {
+  if constexpr (N == 0) {
+    return cell_min<0>(own, dg, xs, ys, match, mismatch, vr, wr_, vc, wc_);
+  } else {
+    if (n >= N) return cell_min<N>(own, dg, xs, ys, match, mismatch, vr, wr_, vc, wc_);
+    return cell_min_n<N - 1>(n, own, dg, xs, ys, match, mismatch, vr, wr_, vc, wc_);
+  }
 }
 
 template <int WKR, int WKC>
@@ -111,55 +149,85 @@ __global__ __launch_bounds__(GAP_THREADS) void k_gap_base(uint32_t* __restrict__
                                                           GapS s) {
   __shared__ uint32_t hr[(GAP_B + 1) * GAP_LS];   // hr[(li + 1) * LS + lj + 1]
   __shared__ uint32_t hc[(GAP_B + 1) * GAP_LS];   // hc[(lj + 1) * LS + li + 1]
-  __shared__ uint32_t wrt[WKR == 1 ? GAP_B * GAP_LS : 1];   // wrt[lj * LS + q] = w(c0 + q, c0 + lj)
-  __shared__ uint32_t wct[WKC == 1 ? GAP_B * GAP_LS : 1];   // wct[li * LS + p] = w'(r0 + p, r0 + li)
+  __shared__ uint32_t wrt[GAP_B * GAP_LS];        // wrt[lj * LS + q] = w(c0 + q, c0 + lj), q < lj
+  __shared__ uint32_t wct[GAP_B * GAP_LS];        // wct[li * LS + p] = w'(r0 + p, r0 + li), p < li
+  __shared__ uint32_t sx[GAP_B], sy[GAP_B];       // symbols of rows r0 + li and columns c0 + lj
   const GapBlock b = blocks[blockIdx.x];
   const int R = (int)(b.r1 - b.r0), C = (int)(b.c1 - b.c0);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < (R + 1) * (C + 1); e += GAP_THREADS) {
-    const int hi = e / (C + 1), hj = e - hi * (C + 1);
-    const int64_t gi = b.r0 + hi - 1, gj = b.c0 + hj - 1;
-    const uint32_t v = (gi >= 0 && gj >= 0) ? gmin(D[gi * ld + gj], G_INF) : G_INF;
-    hr[hi * GAP_LS + hj] = v;
-    hc[hj * GAP_LS + hi] = v;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // halo and block: wave wv takes rows wv, wv + 16, ...; every load first
+  {
+    uint32_t hv[GAP_HROWS][2];
+#pragma unroll
+    for (int a = 0; a < GAP_HROWS; ++a) {
+#pragma unroll
+      for (int c2 = 0; c2 < 2; ++c2) {
+        const int hi = wv + GAP_WAVES * a, hj = lane + 64 * c2;
+        const int64_t gi = b.r0 + hi - 1, gj = b.c0 + hj - 1;
+        hv[a][c2] = (hi <= R && hj <= C && gi >= 0 && gj >= 0) ? gmin(D[gi * ld + gj], G_INF) : G_INF;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < GAP_HROWS; ++a) {
+#pragma unroll
+      for (int c2 = 0; c2 < 2; ++c2) {
+        const int hi = wv + GAP_WAVES * a, hj = lane + 64 * c2;
+        if (hi <= GAP_B && hj <= GAP_B) {
+          hr[hi * GAP_LS + hj] = hv[a][c2];
+          hc[hj * GAP_LS + hi] = hv[a][c2];
+        }
+      }
+    }
   }
   for (int e = tid; e < GAP_B * GAP_B; e += GAP_THREADS) {
     const int x = e / GAP_B, y = e - x * GAP_B;   // target x, source y
-    if constexpr (WKR == 1) wrt[x * GAP_LS + y] = gw<1>(wr, (uint32_t)(b.c0 + y), (uint32_t)(b.c0 + x));
-    if constexpr (WKC == 1) wct[x * GAP_LS + y] = gw<1>(wc, (uint32_t)(b.r0 + y), (uint32_t)(b.r0 + x));
+    wrt[x * GAP_LS + y] = y < x ? gw<WKR>(wr, (uint32_t)(b.c0 + y), (uint32_t)(b.c0 + x)) : GAP_NOPE;
+    wct[x * GAP_LS + y] = y < x ? gw<WKC>(wc, (uint32_t)(b.r0 + y), (uint32_t)(b.r0 + x)) : GAP_NOPE;
+  }
+  if (tid < GAP_B) {
+    sx[tid] = gfmix((uint32_t)(b.r0 + tid) ^ s.seedx) & s.mask;
+  } else if (tid < 2 * GAP_B) {
+    sy[tid - GAP_B] = gfmix((uint32_t)(b.c0 + tid - GAP_B) ^ s.seedy) & s.mask;
   }
   __syncthreads();
   const int u = tid & (GAP_TPC - 1);
   const int cell = tid / GAP_TPC;
   for (int dd = 0; dd <= R + C - 2; ++dd) {
-    const int li = (dd - (C - 1) > 0 ? dd - (C - 1) : 0) + cell;
-    const int lj = dd - li;
-    const bool live = li < R && lj >= 0 && li <= dd;
-    uint32_t acc = G_INF;
-    if (live) {
-      const int64_t gi = b.r0 + li, gj = b.c0 + lj;
-      acc = hr[(li + 1) * GAP_LS + lj + 1];
-      if (u == 0 && gi >= 1 && gj >= 1) acc = gmin(acc, hr[li * GAP_LS + lj] + gs(s, (uint32_t)gi, (uint32_t)gj));
-      // affine: w(c0 + u + T k, c0 + lj) = a + b (lj - u) - T b k, T = GAP_TPC
-      acc = scan_slots<WKR>(acc, hr + (li + 1) * GAP_LS + 1, wrt + (WKR == 1 ? lj * GAP_LS : 0), u, lj,
-                       wr.a + wr.b * (uint32_t)(lj - u), wr.b * GAP_TPC);
-      acc = scan_slots<WKC>(acc, hc + (lj + 1) * GAP_LS + 1, wct + (WKC == 1 ? li * GAP_LS : 0), u, li,
-                       wc.a + wc.b * (uint32_t)(li - u), wc.b * GAP_TPC);
-    }
-    acc = gmin(min16(acc), G_INF);
-    if (live && u == 0) {
-      hr[(li + 1) * GAP_LS + lj + 1] = acc;
-      hc[(lj + 1) * GAP_LS + li + 1] = acc;
+    const int lo = dd - (C - 1) > 0 ? dd - (C - 1) : 0;   // first and last row on the diagonal
+    const int hi = dd < R - 1 ? dd : R - 1;
+    if (GAP_CPW * wv <= hi - lo) {
+      const int li0 = lo + cell;
+      const bool live = li0 <= hi;
+      const int li = live ? li0 : lo, lj = dd - li;   // lanes past the diagonal's end read a real cell
+      const int lr = dd < C - 1 ? dd : C - 1;   // longest row (lr) or column (hi) span on the diagonal
+      const int n = ((lr > hi ? lr : hi) + GAP_TPC - 1) / GAP_TPC;
+      // the diagonal term reads the halo's INF row / column at the grid's first row and column
+      const uint32_t* own = hr + (li + 1) * GAP_LS + lj + 1;
+      const uint32_t* dg = hr + li * GAP_LS + lj;
+      const uint32_t* vr = hr + (li + 1) * GAP_LS + 1 + u;
+      const uint32_t* wr_ = wrt + lj * GAP_LS + u;
+      const uint32_t* vc = hc + (lj + 1) * GAP_LS + 1 + u;
+      const uint32_t* wc_ = wct + li * GAP_LS + u;
+      uint32_t acc = cell_min_n<GAP_B / GAP_TPC>(n, own, dg, sx + li, sy + lj, s.match, s.mismatch, vr, wr_, vc,
+                                                 wc_);
+      acc = gmin(min_group(acc), G_INF);
+      if (live && u < 2) {
+        if (u == 0) hr[(li + 1) * GAP_LS + lj + 1] = acc;
+        else hc[(lj + 1) * GAP_LS + li + 1] = acc;
+      }
     }
     __syncthreads();
   }
-  for (int e = tid; e < R * C; e += GAP_THREADS) {
-    const int li = e / C, lj = e - li * C;
-    D[(b.r0 + li) * ld + b.c0 + lj] = hr[(li + 1) * GAP_LS + lj + 1];
+#pragma unroll
+  for (int a = 0; a < GAP_B / GAP_WAVES; ++a) {
+    const int li = wv + GAP_WAVES * a, lj = lane;
+    if (li < R && lj < C) D[(b.r0 + li) * ld + b.c0 + lj] = hr[(li + 1) * GAP_LS + lj + 1];
   }
-  for (int e = tid; e < R * C; e += GAP_THREADS) {
-    const int lj = e / R, li = e - lj * R;
-    DT[(b.c0 + lj) * ldt + b.r0 + li] = hc[(lj + 1) * GAP_LS + li + 1];
+#pragma unroll
+  for (int a = 0; a < GAP_B / GAP_WAVES; ++a) {
+    const int lj = wv + GAP_WAVES * a, li = lane;
+    if (lj < C && li < R) DT[(b.c0 + lj) * ldt + b.r0 + li] = hc[(lj + 1) * GAP_LS + li + 1];
   }
 }
 
