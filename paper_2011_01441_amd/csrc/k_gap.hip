@@ -84,6 +84,7 @@ constexpr int GAP_THREADS = GAP_B * GAP_TPC;
 constexpr int GAP_WAVES = GAP_THREADS / 64;
 constexpr int GAP_CPW = 64 / GAP_TPC;   // cells per wave
 constexpr int GAP_LS = GAP_B + GAP_TPC;   // LDS row stride in words (GAP_TPC mod 64 banks)
+constexpr int GAP_SLOTS = GAP_B / GAP_TPC;   // slots a side at most
 constexpr int GAP_HROWS = (GAP_B + 1 + GAP_WAVES - 1) / GAP_WAVES;   // halo rows per wave
 // weight-table entry of a source at or after the target: values are at most
 // INF = 2^30, so value + GAP_NOPE > INF and stays below 2^32
@@ -102,44 +103,50 @@ __device__ __forceinline__ uint32_t min_group(uint32_t v) {
   return v;
 }
 
-// a cell's minimum: its own value, its diagonal term (the value up-left
-// plus the substitution cost), N slots of its row predecessors (values vr,
-// weights wr_) and N of its column predecessors (vc, wc_), slot k at
-// GAP_TPC k; every read is issued before the first sum
+// LDS of a base block, one array so that regions read with the same index
+// sit within an instruction's offset range of each other: hr / wct (indexed
+// by the row) and hc / wrt (indexed by the column)
+constexpr int GAP_HSZ = (GAP_B + 1) * GAP_LS, GAP_WSZ = GAP_B * GAP_LS;
+constexpr int GAP_HR = 0;                      // hr[(li + 1) * LS + lj + 1]
+constexpr int GAP_WCT = GAP_HR + GAP_HSZ;      // wct[li * LS + p] = w'(r0 + p, r0 + li), p < li
+constexpr int GAP_HC = GAP_WCT + GAP_WSZ;      // hc[(lj + 1) * LS + li + 1]
+constexpr int GAP_WRT = GAP_HC + GAP_HSZ;      // wrt[lj * LS + q] = w(c0 + q, c0 + lj), q < lj
+constexpr int GAP_SX = GAP_WRT + GAP_WSZ;      // symbols of rows r0 + li
+constexpr int GAP_SY = GAP_SX + GAP_B;         // symbols of columns c0 + lj
+constexpr int GAP_LDS = GAP_SY + GAP_B;
+
+// One anti-diagonal dd for one thread, N slots a side: the cell's own value,
+// its diagonal term (the value up-left plus the substitution cost), N slots
+// of its row predecessors and N of its column predecessors (slot k at
+// GAP_TPC k), every read issued before the first sum; the group's minimum is
+// stored by its first two lanes (row-major and column-major copy).
 template <int N>
-__device__ __forceinline__ uint32_t cell_min(const uint32_t* own, const uint32_t* dg, const uint32_t* xs,
-                                             const uint32_t* ys, uint32_t match, uint32_t mismatch,
-                                             const uint32_t* vr, const uint32_t* wr_, const uint32_t* vc,
-                                             const uint32_t* wc_) {
+__device__ __forceinline__ void gap_diag(uint32_t* L, int dd, int R, int C, int wv, int cell, int u,
+                                         const GapS& s) {
+  const int lo = dd - (C - 1) > 0 ? dd - (C - 1) : 0;   // first and last row on the diagonal
+  const int hi = dd < R - 1 ? dd : R - 1;
+  if (GAP_CPW * wv > hi - lo) return;                   // no cell of this wave on the diagonal
+  const int li0 = lo + cell;
+  const bool live = li0 <= hi;
+  const int li = li0 < hi ? li0 : hi, lj = dd - li;    // lanes past the diagonal's end read a real cell
+  const int rc = li * GAP_LS + lj;                      // (li + 1, lj + 1) in hr, less LS + 1
+  const int ru = li * GAP_LS + u, cu = lj * GAP_LS + u;
   uint32_t v[2 * N + 1], w[2 * N + 1];
-  const uint32_t acc0 = *own, sxv = *xs, syv = *ys;
-  v[2 * N] = *dg;
+  const uint32_t own = L[GAP_HR + rc + GAP_LS + 1], sxv = L[GAP_SX + li], syv = L[GAP_SY + lj];
+  v[2 * N] = L[GAP_HR + rc];   // the halo's INF row / column covers the grid's first row and column
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    v[k] = vr[GAP_TPC * k];
-    w[k] = wr_[GAP_TPC * k];
-    v[N + k] = vc[GAP_TPC * k];
-    w[N + k] = wc_[GAP_TPC * k];
+    v[k] = L[GAP_HR + ru + GAP_LS + 1 + GAP_TPC * k];
+    w[k] = L[GAP_WRT + cu + GAP_TPC * k];
+    v[N + k] = L[GAP_HC + cu + GAP_LS + 1 + GAP_TPC * k];
+    w[N + k] = L[GAP_WCT + ru + GAP_TPC * k];
   }
-  w[2 * N] = sxv == syv ? match : mismatch;
-  uint32_t acc = acc0;
+  w[2 * N] = sxv == syv ? s.match : s.mismatch;
+  uint32_t acc = own;
 #pragma unroll
   for (int k = 0; k < 2 * N + 1; ++k) acc = gmin(acc, v[k] + w[k]);
-  return acc;
-}
-
-// cell_min with the slot count n (block-uniform, 0..N) as a template argument
-template <int N>
-__device__ __forceinline__ uint32_t cell_min_n(int n, const uint32_t* own, const uint32_t* dg, const uint32_t* xs,
-                                               const uint32_t* ys, uint32_t match, uint32_t mismatch,
-                                               const uint32_t* vr, const uint32_t* wr_, const uint32_t* vc,
-                                               const uint32_t* wc_) {
-  if constexpr (N == 0) {
-    return cell_min<0>(own, dg, xs, ys, match, mismatch, vr, wr_, vc, wc_);
-  } else {
-    if (n >= N) return cell_min<N>(own, dg, xs, ys, match, mismatch, vr, wr_, vc, wc_);
-    return cell_min_n<N - 1>(n, own, dg, xs, ys, match, mismatch, vr, wr_, vc, wc_);
-  }
+  acc = gmin(min_group(acc), G_INF);
+  if (live && u < 2) L[u == 0 ? GAP_HR + rc + GAP_LS + 1 : GAP_HC + lj * GAP_LS + li + GAP_LS + 1] = acc;
 }
 
 template <int WKR, int WKC>
@@ -147,16 +154,14 @@ __global__ __launch_bounds__(GAP_THREADS) void k_gap_base(uint32_t* __restrict__
                                                           uint32_t* __restrict__ DT, int64_t ldt,
                                                           const GapBlock* __restrict__ blocks, GapW wr, GapW wc,
                                                           GapS s) {
-  __shared__ uint32_t hr[(GAP_B + 1) * GAP_LS];   // hr[(li + 1) * LS + lj + 1]
-  __shared__ uint32_t hc[(GAP_B + 1) * GAP_LS];   // hc[(lj + 1) * LS + li + 1]
-  __shared__ uint32_t wrt[GAP_B * GAP_LS];        // wrt[lj * LS + q] = w(c0 + q, c0 + lj), q < lj
-  __shared__ uint32_t wct[GAP_B * GAP_LS];        // wct[li * LS + p] = w'(r0 + p, r0 + li), p < li
-  __shared__ uint32_t sx[GAP_B], sy[GAP_B];       // symbols of rows r0 + li and columns c0 + lj
+  __shared__ uint32_t L[GAP_LDS];
+  uint32_t* hr = L + GAP_HR;
+  uint32_t* hc = L + GAP_HC;
   const GapBlock b = blocks[blockIdx.x];
   const int R = (int)(b.r1 - b.r0), C = (int)(b.c1 - b.c0);
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // halo and block: wave wv takes rows wv, wv + 16, ...; every load first
+  // halo and block: wave wv takes rows wv, wv + GAP_WAVES, ...; every load first
   {
     uint32_t hv[GAP_HROWS][2];
 #pragma unroll
@@ -182,43 +187,39 @@ __global__ __launch_bounds__(GAP_THREADS) void k_gap_base(uint32_t* __restrict__
   }
   for (int e = tid; e < GAP_B * GAP_B; e += GAP_THREADS) {
     const int x = e / GAP_B, y = e - x * GAP_B;   // target x, source y
-    wrt[x * GAP_LS + y] = y < x ? gw<WKR>(wr, (uint32_t)(b.c0 + y), (uint32_t)(b.c0 + x)) : GAP_NOPE;
-    wct[x * GAP_LS + y] = y < x ? gw<WKC>(wc, (uint32_t)(b.r0 + y), (uint32_t)(b.r0 + x)) : GAP_NOPE;
+    L[GAP_WRT + x * GAP_LS + y] = y < x ? gw<WKR>(wr, (uint32_t)(b.c0 + y), (uint32_t)(b.c0 + x)) : GAP_NOPE;
+    L[GAP_WCT + x * GAP_LS + y] = y < x ? gw<WKC>(wc, (uint32_t)(b.r0 + y), (uint32_t)(b.r0 + x)) : GAP_NOPE;
   }
   if (tid < GAP_B) {
-    sx[tid] = gfmix((uint32_t)(b.r0 + tid) ^ s.seedx) & s.mask;
+    L[GAP_SX + tid] = gfmix((uint32_t)(b.r0 + tid) ^ s.seedx) & s.mask;
   } else if (tid < 2 * GAP_B) {
-    sy[tid - GAP_B] = gfmix((uint32_t)(b.c0 + tid - GAP_B) ^ s.seedy) & s.mask;
+    L[GAP_SY + tid - GAP_B] = gfmix((uint32_t)(b.c0 + tid - GAP_B) ^ s.seedy) & s.mask;
   }
   __syncthreads();
   const int u = tid & (GAP_TPC - 1);
   const int cell = tid / GAP_TPC;
-  for (int dd = 0; dd <= R + C - 2; ++dd) {
-    const int lo = dd - (C - 1) > 0 ? dd - (C - 1) : 0;   // first and last row on the diagonal
-    const int hi = dd < R - 1 ? dd : R - 1;
-    if (GAP_CPW * wv <= hi - lo) {
-      const int li0 = lo + cell;
-      const bool live = li0 <= hi;
-      const int li = live ? li0 : lo, lj = dd - li;   // lanes past the diagonal's end read a real cell
-      const int lr = dd < C - 1 ? dd : C - 1;   // longest row (lr) or column (hi) span on the diagonal
-      const int n = ((lr > hi ? lr : hi) + GAP_TPC - 1) / GAP_TPC;
-      // the diagonal term reads the halo's INF row / column at the grid's first row and column
-      const uint32_t* own = hr + (li + 1) * GAP_LS + lj + 1;
-      const uint32_t* dg = hr + li * GAP_LS + lj;
-      const uint32_t* vr = hr + (li + 1) * GAP_LS + 1 + u;
-      const uint32_t* wr_ = wrt + lj * GAP_LS + u;
-      const uint32_t* vc = hc + (lj + 1) * GAP_LS + 1 + u;
-      const uint32_t* wc_ = wct + li * GAP_LS + u;
-      uint32_t acc = cell_min_n<GAP_B / GAP_TPC>(n, own, dg, sx + li, sy + lj, s.match, s.mismatch, vr, wr_, vc,
-                                                 wc_);
-      acc = gmin(min_group(acc), G_INF);
-      if (live && u < 2) {
-        if (u == 0) hr[(li + 1) * GAP_LS + lj + 1] = acc;
-        else hc[(lj + 1) * GAP_LS + li + 1] = acc;
-      }
-    }
-    __syncthreads();
+  // The slot count a diagonal needs, ceil(min(dd, max(R, C) - 1) / GAP_TPC),
+  // grows with dd and then stays: the diagonals run in segments of one count
+  // (segment N ends at dd = GAP_TPC N, the last one at the block's end).
+  const int last = R + C - 2;
+  const int mx = (R > C ? R : C) - 1;
+  const int nmax = (mx + GAP_TPC - 1) / GAP_TPC;
+  int dd = 0;
+#define GAP_SEGMENT(N)                                                        \
+  if constexpr (N <= GAP_SLOTS) {                                             \
+    if (N <= nmax) {                                                          \
+      const int end = N == nmax ? last + 1 : GAP_TPC * N + 1;                 \
+      for (; dd < end; ++dd) {                                                \
+        gap_diag<N>(L, dd, R, C, wv, cell, u, s);                             \
+        __syncthreads();                                                      \
+      }                                                                       \
+    }                                                                         \
   }
+  GAP_SEGMENT(0) GAP_SEGMENT(1) GAP_SEGMENT(2) GAP_SEGMENT(3) GAP_SEGMENT(4)
+  GAP_SEGMENT(5) GAP_SEGMENT(6) GAP_SEGMENT(7) GAP_SEGMENT(8)
+  GAP_SEGMENT(9) GAP_SEGMENT(10) GAP_SEGMENT(11) GAP_SEGMENT(12)
+  GAP_SEGMENT(13) GAP_SEGMENT(14) GAP_SEGMENT(15) GAP_SEGMENT(16)
+#undef GAP_SEGMENT
 #pragma unroll
   for (int a = 0; a < GAP_B / GAP_WAVES; ++a) {
     const int li = wv + GAP_WAVES * a, lj = lane;
