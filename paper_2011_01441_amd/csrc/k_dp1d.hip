@@ -49,6 +49,36 @@ __device__ __forceinline__ uint32_t load_dev(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Inputs [i0 + t0, i0 + t0 + cnt) of a finished block (lane t of `vin`
+// holds input i0 + t; affine: with -b i folded in) applied to the outputs
+// [o_beg, len) of the triangle, merged into d by LDS atomic minima.  cnt <=
+// MAXK; slots past cnt take 2^31, which no sum with a weight <= 2^30 brings
+// below a real candidate.
+template <int WK, int MAXK>
+__device__ __forceinline__ void tri_apply(uint32_t vin, int t0, int cnt, uint32_t i0, int64_t lo, int o_beg, int len,
+                                          const DpW& w, uint32_t* d) {
+  const int lane = threadIdx.x & 63;
+  uint32_t sv[MAXK];
+#pragma unroll
+  for (int k = 0; k < MAXK; ++k)
+    sv[k] = k < cnt ? (uint32_t)__builtin_amdgcn_readlane((int)vin, t0 + k) : 0x80000000u;
+#pragma unroll 1
+  for (int o0 = o_beg; o0 < len; o0 += 64) {
+    const int o = o0 + lane;
+    const uint32_t j = (uint32_t)(lo + o);
+    uint32_t acc = DP_INF;
+    if constexpr (WK == 0) {
+      const uint32_t cj = w.a + w.b * j;
+#pragma unroll
+      for (int k = 0; k < MAXK; ++k) acc = umin(acc, sv[k] + cj);
+    } else {
+#pragma unroll
+      for (int k = 0; k < MAXK; ++k) acc = umin(acc, sv[k] + wval<WK>(w, i0 + (uint32_t)(t0 + k), j));
+    }
+    if (o < len) atomicMin(d + o, acc);
+  }
+}
+
 // A base triangle: positions [lo, lo + len), len <= DP_TRI_MAX, whose values
 // already hold every update from inputs below lo; run by all 256 threads of
 // one workgroup.  Per block of 64 outputs:
@@ -56,17 +86,19 @@ __device__ __forceinline__ uint32_t load_dev(const uint32_t* p) {
 //     LDS (2^31 where t >= l: dt + 2^31 < 2^32 never wins a minimum);
 //  2. wave 0 walks the chain: output t is final once every earlier output of
 //     the block has been applied to it, so lane t's value is read as a
-//     wave-uniform scalar and applied to the lanes after it;
-//  3. every wave takes a quarter of the finished block's inputs (read out
-//     of one register by lane reads, once per block) and applies them to
-//     every later output of the triangle; the waves' minima meet by LDS
-//     atomic minima.
+//     wave-uniform scalar and applied to the lanes after it.  Meanwhile waves
+//     1-3 apply the previous block (22, 21 and 21 of its inputs) to every
+//     output after this block;
+//  3. all four waves apply this block (16 inputs each) to the next block's
+//     64 outputs only, so that the next chain can start.
+// An input block thus reaches the next block at step 3 and every later one
+// during the next block's chain; the waves' minima meet by LDS atomic minima.
 template <int WK>
 __device__ void tri_body(uint32_t* __restrict__ D, int64_t lo, int len, const DpW& w, uint32_t* d,
                          uint32_t* wl) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wv = tid >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int t = tid; t < len; t += 256) d[t] = umin(load_dev(D + lo + t), DP_INF);
   for (int blk = 0; blk < len; blk += 64) {
 #pragma unroll
@@ -76,7 +108,7 @@ __device__ void tri_body(uint32_t* __restrict__ D, int64_t lo, int len, const Dp
       wl[e] = l > t ? wval<WK>(w, (uint32_t)(lo + blk + t), (uint32_t)(lo + blk + l)) : 0x80000000u;
     }
     __syncthreads();   // weights written; d holds every update of earlier blocks
-    if (tid < 64) {
+    if (wv == 0) {
       uint32_t acc = blk + lane < len ? d[blk + lane] : DP_INF;
       // weights in chunks of 16 steps, the next chunk requested before the
       // current one is walked (32 registers instead of 64)
@@ -100,36 +132,25 @@ __device__ void tri_body(uint32_t* __restrict__ D, int64_t lo, int len, const Dp
         for (int t = 0; t < 16; ++t) wa[t] = wb[t];
       }
       if (blk + lane < len) d[blk + lane] = umin(acc, DP_INF);
+    } else if (blk >= 64 && blk + 64 < len) {
+      // the previous block's inputs reach every output after this block
+      const int pb = blk - 64;
+      const uint32_t i0 = (uint32_t)(lo + pb);
+      const uint32_t vin = WK == 0 ? d[pb + lane] - w.b * (i0 + (uint32_t)lane) : d[pb + lane];
+      const int t0 = wv == 1 ? 0 : (wv == 2 ? 22 : 43);
+      tri_apply<WK, 22>(vin, t0, wv == 1 ? 22 : 21, i0, lo, blk + 64, len, w, d);
     }
-    __syncthreads();   // the block is final
+    __syncthreads();   // the block is final; the previous block reached every later output
     if (blk + 64 < len) {
       const uint32_t i0 = (uint32_t)(lo + blk);
       // lane t: input blk + t; affine weights fold their input-only part
       // -b i into it, so D[i] + w(i, j) = vin_t + (a + b j)
       const uint32_t vin = WK == 0 ? d[blk + lane] - w.b * (i0 + (uint32_t)lane) : d[blk + lane];
-      // wave v applies inputs blk + 16 v .. blk + 16 v + 15 to every later
-      // output; the four waves' minima meet in LDS (atomic minimum)
-      const int t0 = 16 * __builtin_amdgcn_readfirstlane(wv);
-      uint32_t sv[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) sv[k] = (uint32_t)__builtin_amdgcn_readlane((int)vin, t0 + k);
-#pragma unroll 1
-      for (int o0 = blk + 64; o0 < len; o0 += 64) {
-        const int o = o0 + lane;
-        const uint32_t j = (uint32_t)(lo + o);
-        uint32_t acc = DP_INF;
-        if constexpr (WK == 0) {
-          const uint32_t cj = w.a + w.b * j;
-#pragma unroll
-          for (int k = 0; k < 16; ++k) acc = umin(acc, sv[k] + cj);
-        } else {
-#pragma unroll
-          for (int k = 0; k < 16; ++k) acc = umin(acc, sv[k] + wval<WK>(w, i0 + (uint32_t)(t0 + k), j));
-        }
-        if (o < len) atomicMin(d + o, acc);
-      }
+      const int nxt = blk + 128 < len ? blk + 128 : len;
+      tri_apply<WK, 16>(vin, 16 * wv, 16, i0, lo, blk + 64, nxt, w, d);
     }
-    // the next block's weight pass touches only wl, which nothing reads now
+    // the next block's weight pass touches only wl, which nothing reads now;
+    // its barrier orders these minima before the next chain
   }
   __syncthreads();
   for (int t = tid; t < len; t += 256) D[lo + t] = d[t];
