@@ -303,6 +303,27 @@ def cpu_sample(w, A, B, target_s):
                       f"{dt:.1f} s", "seconds": dt}
 
 
+def vendor_ring(torch, w, Ad, Bd, steps):
+    """The ROCm BLAS libraries (through torch.matmul, 2-D, contiguous
+    operands) on the same operands and device: an FP32 GEMM, and one BF16
+    GEMM of the operands rounded once to bfloat16 (one matrix-core product
+    per output term, where bf16x3 takes three).  A reported baseline: it
+    shows what the vendor's GEMM reaches on this shape under the same power
+    limit."""
+    n, m, k = w["n"], w["m"], w["k"]
+    flops = 2.0 * n * m * k
+    out = {"library": "torch.matmul (hipBLASLt / rocBLAS)", "flops_per_gemm": flops}
+    Ab, Bb = Ad.to(torch.bfloat16), Bd.to(torch.bfloat16)
+    for name, fn in (("fp32", lambda: torch.matmul(Ad, Bd)), ("bf16", lambda: torch.matmul(Ab, Bb))):
+        for _ in range(3):
+            fn()
+        t = timed(torch, fn, max(steps, 10))
+        out[name + "_ms"] = round(t * 1e3, 4)
+        out[name + "_tflops"] = round(flops / t / 1e12, 1)
+    del Ab, Bb
+    return out
+
+
 def bench_server(torch, P, count, rate, check=32):
     """Open-loop and saturation runs of the request server, batched vs
     per-request launches, on views of resident operand pools."""
@@ -398,6 +419,8 @@ def main():
                     help="ring workloads: skip the measured processor throughputs (equal weights)")
     ap.add_argument("--no-graph", action="store_true", help="skip the hipGraph replay timing")
     ap.add_argument("--no-peaks", action="store_true", help="skip the device peak probes")
+    ap.add_argument("--no-vendor", action="store_true",
+                    help="ring workloads: skip the vendor-library GEMM baseline")
     ap.add_argument("--hold", type=float, default=0.0,
                     help="after the JSON line, keep running the step for this many seconds "
                          "(for sampling clocks and power from outside)")
@@ -592,6 +615,12 @@ def main():
                "relative_to_C64": math.sqrt(sd / sr) if sr > 0 else None,
                "max_rel_componentwise_sampled": mrel, "rows": int(rows.numel()), "bound": 2.0 ** -16}
 
+    vendor = None
+    if w["kind"] == "ring" and not args.no_vendor:
+        vendor = vendor_ring(torch, w, Ad, Bd, args.steps)
+        log(f"vendor GEMM: fp32 {vendor['fp32_ms']} ms, bf16 {vendor['bf16_ms']} ms "
+            f"({vendor['bf16_tflops']} TFLOP/s)")
+
     server = None
     if not args.no_server:
         server = bench_server(torch, P, args.server_requests, 2000.0)
@@ -642,6 +671,7 @@ def main():
         "paco_vs_grid": round(grid["ms_per_step"] / ms, 4) if grid else None,
         "graph_replay": graph,
         "classic_baseline": classic,
+        "vendor_baseline": vendor,
         "strassen_vs_classic": round(classic["ms_per_step"] / ms, 4) if classic else None,
         "error": err,
         "server": server,
