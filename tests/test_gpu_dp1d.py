@@ -1,5 +1,6 @@
 """The 1D problem on the GPU (paco_dp1d) against the oracle, bit-exact:
-sizes spanning several base triangles, ragged ends, p not a power of two,
+sizes spanning several base triangles, single triangles of many lengths,
+ragged ends, p not a power of two,
 both partitions, both weight families, repeated calls on one plan, the
 degenerate sizes, and a full-size run checked on sampled outputs."""
 import numpy as np
@@ -39,6 +40,18 @@ def test_small_sizes(ctx, n, kind, a, b):
     print(f"dp1d n={n} {kind}", flush=True)
     got, _ = run(ctx, n, kind, a, b, seed=3, d0=11)
     assert np.array_equal(got, oracle.dp1d(n, kind, a, b, 3, 11))
+
+
+# one base triangle of n + 1 positions (base 1024): the next block's update
+# runs from two 64-position blocks on, the far update beside the chain from
+# three; lengths on both sides of those counts, ragged last blocks, the
+# largest triangle
+@pytest.mark.parametrize("n", [127, 128, 129, 191, 192, 193, 320, 447, 448, 1023])
+@pytest.mark.parametrize("kind,a,b", [("hash", 1, 19), ("affine", 2, 7)])
+def test_one_triangle_lengths(ctx, n, kind, a, b):
+    print(f"dp1d one triangle n={n} {kind}", flush=True)
+    got, _ = run(ctx, n, kind, a, b, seed=5, d0=2, base=1024)
+    assert np.array_equal(got, oracle.dp1d(n, kind, a, b, 5, 2))
 
 
 @pytest.mark.parametrize("part,p,base,minp", [("paco", 0, 0, 0), ("paco", 97, 64, 64), ("paco", 1000, 1024, 4096),

@@ -1,5 +1,6 @@
 """The GAP problem on the GPU (paco_gap) against the oracle, bit-exact:
-degenerate and ragged grids, one to many base blocks, both partitions,
+degenerate and ragged grids, single base blocks of many shapes, one to many
+base blocks, both partitions,
 p not a power of two, both weight families, repeated calls on one plan, a
 padded leading dimension, and a full-size grid checked at sampled cells."""
 import numpy as np
@@ -43,6 +44,20 @@ def test_sizes(ctx, m, n, w):
     print(f"gap m={m} n={n} {w[0][0]}", flush=True)
     got, _ = run(ctx, m, n, *w, d0=3)
     assert np.array_equal(got, oracle.gap(m, n, *w, d0=3))
+
+
+# grids of one base block (R x C cells, R, C <= 64): the block's
+# anti-diagonals run in loops of one slot count per side, which changes where
+# max(R, C) - 1 crosses 16, 32 and 48; square, flat and tall blocks on both
+# sides of each change
+@pytest.mark.parametrize("R,C", [(16, 16), (17, 17), (18, 5), (5, 18), (33, 2), (2, 33), (34, 50), (50, 34),
+                                 (49, 49), (64, 17), (17, 64), (64, 1), (1, 64), (64, 64)])
+@pytest.mark.parametrize("w", [WH, WA])
+def test_single_block_shapes(ctx, R, C, w):
+    print(f"gap one block {R}x{C} {w[0][0]}", flush=True)
+    got, r = run(ctx, R - 1, C - 1, *w, d0=1)
+    assert r["base_blocks"] == 1
+    assert np.array_equal(got, oracle.gap(R - 1, C - 1, *w, d0=1))
 
 
 @pytest.mark.parametrize("part,p,minp", [("paco", 0, 0), ("paco", 37, 500), ("paco", 1, 1), ("grid", 0, 0),
