@@ -155,8 +155,10 @@ typedef struct paco_mm_desc {
                                    k / kcut_cost (1 = the paper's rule; a
                                    k-cut costs a temporary face written and
                                    read back); 0 = library default: 16
-                                   for the ring, chosen among 1, 4 and 16
-                                   with the tile and p for the others */
+                                   for the ring, chosen among 1, 4, 16 and
+                                   64 with the tile and p for the others;
+                                   values below 1, or not finite, are
+                                   PACO_ERR_INVALID_ARG */
   const double* weights;        /* NULL, or p positive processor throughputs
                                    (host memory, read during the call): PACO
                                    mode with an explicit p cuts each cuboid
@@ -179,7 +181,17 @@ typedef struct paco_mm_result {
 } paco_mm_result;
 
 /* Extended form: explicit leading dimensions, accumulation, precision,
- * partition mode and processor count.  `out` may be NULL. */
+ * partition mode and processor count.  `out` may be NULL.
+ *
+ * Environment overrides, read when a plan is built (for experiments and
+ * the tile-grid baseline's autotuning; each value is part of the plan-cache
+ * key, so changing it builds a new plan):
+ *   PACO_KCUT_COST  k-cut cost used when the caller gives 0 (values below 1
+ *                   count as 1);
+ *   PACO_RING_TILE, PACO_INT_TILE, PACO_BOOL_TILE
+ *                   index of the tile shape of the ring, (min,+)/(max,+) or
+ *                   boolean kernel, overriding the chosen one (out-of-range
+ *                   values are ignored). */
 paco_status paco_semiring_mm_ex(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* out);
 
 /* Measure the throughput of p processors (workgroups of one launch, p a
