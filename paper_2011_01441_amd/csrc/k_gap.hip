@@ -238,7 +238,7 @@ __global__ __launch_bounds__(GAP_THREADS) void k_gap_base(uint32_t* __restrict__
 // D[o][t] = min over x of DT[t][x] + w'(x, o).  A wave takes one batch index,
 // four 64-output strips (four outputs per lane; one strip when the piece is
 // at most 128 outputs wide) and a slice of the inputs, read 8 at a time as
-// wave-uniform values.
+// wave-uniform values (affine weights: 16 at a time, in two alternating sets).
 constexpr int GR = 4;
 
 template <int WK, int NR>
@@ -252,6 +252,35 @@ __device__ __forceinline__ void cube_unit(uint32_t* __restrict__ D, int64_t ld, 
     acc[r] = G_INF;
   }
   int64_t x = xa;
+  if constexpr (WK == 0) {
+    // affine weights cost about two instructions a pair, too few to cover a
+    // load from HBM: two sets of 16 inputs alternate, each requested while
+    // the other is applied
+    constexpr int CH = 16;
+    if (x + 2 * CH <= xb) {
+      uint32_t va[CH], vb[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) va[k] = src[x + k];
+      for (; x + 2 * CH <= xb; x += 2 * CH) {
+#pragma unroll
+        for (int k = 0; k < CH; ++k) vb[k] = src[x + CH + k];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) acc[r] = gmin(acc[r], va[k] + gw<WK>(w, (uint32_t)(x + k), ou[r]));
+        }
+        if (x + 4 * CH <= xb) {
+#pragma unroll
+          for (int k = 0; k < CH; ++k) va[k] = src[x + 2 * CH + k];
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) acc[r] = gmin(acc[r], vb[k] + gw<WK>(w, (uint32_t)(x + CH + k), ou[r]));
+        }
+      }
+    }
+  }
   for (; x + 8 <= xb; x += 8) {
     uint32_t dv[8];
 #pragma unroll
@@ -274,15 +303,14 @@ __device__ __forceinline__ void cube_unit(uint32_t* __restrict__ D, int64_t ld, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_gap_cube(uint32_t* __restrict__ D, int64_t ld, const uint32_t* __restrict__ DT,
-                                                  int64_t ldt, const GapPiece* __restrict__ pieces, GapW wr, GapW wc) {
-  const GapPiece pc = pieces[blockIdx.x];
+// one piece's units with the weight kind WK of its direction
+template <int WK>
+__device__ __forceinline__ void cube_piece(uint32_t* __restrict__ D, int64_t ld, const uint32_t* __restrict__ DT,
+                                           int64_t ldt, const GapPiece& pc, const GapW& w) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t T = pc.t1 - pc.t0, W = pc.o1 - pc.o0, H = pc.x1 - pc.x0;
-  if (T <= 0 || W <= 0 || H <= 0) return;
   const bool col = pc.col != 0;
-  const GapW w = col ? wc : wr;
   // narrow pieces (at most two strips) take one 64-output strip per unit
   const int nr = W <= 128 ? 1 : GR;
   const int64_t groups = (W + 64 * nr - 1) / (64 * nr);
@@ -296,18 +324,21 @@ __global__ __launch_bounds__(256) void k_gap_cube(uint32_t* __restrict__ D, int6
     const int64_t ob = pc.o0 + g * 64 * nr + lane;
     const int64_t xa = pc.x0 + H * slice / S, xb = pc.x0 + H * (slice + 1) / S;
     const uint32_t* src = col ? DT + t * ldt : D + t * ld;
-    if (nr == 1) {
-      if (w.kind == 0) {
-        cube_unit<0, 1>(D, ld, src, col, t, ob, pc.o1, xa, xb, w);
-      } else {
-        cube_unit<1, 1>(D, ld, src, col, t, ob, pc.o1, xa, xb, w);
-      }
-    } else if (w.kind == 0) {
-      cube_unit<0, GR>(D, ld, src, col, t, ob, pc.o1, xa, xb, w);
-    } else {
-      cube_unit<1, GR>(D, ld, src, col, t, ob, pc.o1, xa, xb, w);
-    }
+    if (nr == 1) cube_unit<WK, 1>(D, ld, src, col, t, ob, pc.o1, xa, xb, w);
+    else cube_unit<WK, GR>(D, ld, src, col, t, ob, pc.o1, xa, xb, w);
   }
+}
+
+// One piece per workgroup; WKR / WKC the weight kinds of the row and column
+// directions (one instantiation each, so that a kind's registers do not
+// limit the other's occupancy).
+template <int WKR, int WKC>
+__global__ __launch_bounds__(256) void k_gap_cube(uint32_t* __restrict__ D, int64_t ld, const uint32_t* __restrict__ DT,
+                                                  int64_t ldt, const GapPiece* __restrict__ pieces, GapW wr, GapW wc) {
+  const GapPiece pc = pieces[blockIdx.x];
+  if (pc.t1 <= pc.t0 || pc.o1 <= pc.o0 || pc.x1 <= pc.x0) return;
+  if (pc.col != 0) cube_piece<WKC>(D, ld, DT, ldt, pc, wc);
+  else cube_piece<WKR>(D, ld, DT, ldt, pc, wr);
 }
 
 }  // namespace
@@ -338,7 +369,16 @@ hipError_t launch_gap_base(uint32_t* D, int64_t ld, uint32_t* DT, int64_t ldt, c
 hipError_t launch_gap_cube(uint32_t* D, int64_t ld, const uint32_t* DT, int64_t ldt, const GapPiece* pieces,
                            int npieces, const GapW& wr, const GapW& wc, hipStream_t s) {
   if (npieces <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gap_cube, dim3(npieces), dim3(256), 0, s, D, ld, DT, ldt, pieces, wr, wc);
+  const dim3 g(npieces), t(256);
+  if (wr.kind == 0 && wc.kind == 0) {
+    hipLaunchKernelGGL((k_gap_cube<0, 0>), g, t, 0, s, D, ld, DT, ldt, pieces, wr, wc);
+  } else if (wr.kind == 0) {
+    hipLaunchKernelGGL((k_gap_cube<0, 1>), g, t, 0, s, D, ld, DT, ldt, pieces, wr, wc);
+  } else if (wc.kind == 0) {
+    hipLaunchKernelGGL((k_gap_cube<1, 0>), g, t, 0, s, D, ld, DT, ldt, pieces, wr, wc);
+  } else {
+    hipLaunchKernelGGL((k_gap_cube<1, 1>), g, t, 0, s, D, ld, DT, ldt, pieces, wr, wc);
+  }
   return hipGetLastError();
 }
 
