@@ -242,9 +242,30 @@ __global__ __launch_bounds__(256) void k_dp1d_rect(const uint32_t* __restrict__ 
         cj[r] = WK == 0 ? w.a + w.b * ju[r] : 0u;   // affine: the output-only part
         acc[r] = DP_INF;
       }
-      // inputs in chunks of CH (one wave-uniform load each), then the rest
+      // inputs in chunks of CH (one wave-uniform load each), then the rest;
+      // affine: two sets of CH alternate, each requested while the other is
+      // applied (a pair is about two instructions, too few to cover a load)
       constexpr int CH = WK == 0 ? 16 : 8;
       int64_t i = ia;
+      if constexpr (WK == 0) {
+        if (i + 2 * CH <= ib) {
+          uint32_t va[CH], vb[CH];
+#pragma unroll
+          for (int k = 0; k < CH; ++k) va[k] = Din[i + k];
+          for (; i + 2 * CH <= ib; i += 2 * CH) {
+#pragma unroll
+            for (int k = 0; k < CH; ++k) vb[k] = Din[i + CH + k];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) rect_in<WK>(acc, va[k], (uint32_t)(i + k), ju, cj, w);
+            if (i + 4 * CH <= ib) {
+#pragma unroll
+              for (int k = 0; k < CH; ++k) va[k] = Din[i + 2 * CH + k];
+            }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) rect_in<WK>(acc, vb[k], (uint32_t)(i + CH + k), ju, cj, w);
+          }
+        }
+      }
       for (; i + CH <= ib; i += CH) {
         uint32_t dv[CH];
 #pragma unroll
