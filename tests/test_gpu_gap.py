@@ -77,6 +77,18 @@ def test_repeated_calls_and_padded_rows(ctx):
         assert np.array_equal(got, oracle.gap(m, n, *w, d0=d0))
 
 
+# one weight family per direction: the base and cube kernels have one
+# instantiation per (row, column) pair of families
+@pytest.mark.parametrize("wr,wc", [(("hash", 1, 11, 5), ("affine", 3, 2, 0)), (("affine", 2, 1, 0), ("hash", 0, 9, 6))])
+@pytest.mark.parametrize("part", ["paco", "grid"])
+def test_mixed_weight_kinds(ctx, wr, wc, part):
+    m, n = 300, 517
+    s = (1, 4, 2, 3, 4)
+    print(f"gap {m}x{n} rows {wr[0]} columns {wc[0]} part={part}", flush=True)
+    got, _ = run(ctx, m, n, wr, wc, s, d0=2, part=part)
+    assert np.array_equal(got, oracle.gap(m, n, wr, wc, s, d0=2))
+
+
 def test_edit_distance_instance(ctx):
     # linear gaps, unit costs over 4 symbols: the Levenshtein distance of two
     # hashed DNA-like strings (the oracle's Wagner-Fischer pin)
