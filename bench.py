@@ -394,9 +394,10 @@ def bench_server(torch, P, count, rate, check=32):
             bad += int(not np.array_equal(got, oracle.minplus(a[rows], b)))
         else:
             C64, S = oracle.ring_f64(a, b, rows=rows, with_abs=True)
-            worst = max(worst, float(np.max(np.abs(got - C64) / S)))
+            e = float(np.max(np.abs(got - C64) / S))
+            worst = math.inf if not math.isfinite(e) else max(worst, e)   # a NaN is a failure
     out["check"] = {"sampled_requests": int(min(check, count)), "minplus_mismatches": bad,
-                    "ring_max_rel": worst}
+                    "ring_max_rel": worst, "ok": bad == 0 and worst <= 2.0 ** -20}
     ctx.close()
     return out
 
@@ -599,8 +600,10 @@ def main():
                "check": "each sampled D[j] equals min over i < j of D[i] + w(i, j) on the GPU's own D"}
     if w["kind"] == "ring":
         _, r = call(ctx, w, Ad, Bd, C, verify_rows=args.verify_rows, return_result=True)
-        err = {"max_rel_componentwise_sampled": r["verify_max_rel"], "rows": args.verify_rows,
-               "bound": 2.0 ** -20, "log2": math.log2(r["verify_max_rel"]) if r["verify_max_rel"] > 0 else None}
+        e = r["verify_max_rel"]
+        ok = math.isfinite(e) and 0 <= e <= 2.0 ** -20      # NaN fails explicitly
+        err = {"max_rel_componentwise_sampled": e if math.isfinite(e) else str(e), "rows": args.verify_rows,
+               "bound": 2.0 ** -20, "log2": math.log2(e) if ok and e > 0 else None, "ok": ok}
     elif w["kind"] == "strassen":
         call(ctx, w, Ad, Bd, C)
         rows = torch.arange(0, w["n"], max(1, w["n"] // 64), device=dev)
@@ -611,9 +614,11 @@ def main():
         nb = float(np.linalg.norm(B.astype(np.float64)))
         diff_f = math.sqrt(sd * w["n"] / rows.numel())
         nw = diff_f / (na * nb)
-        err = {"normwise": nw, "log2": math.log2(nw) if nw > 0 else None,
-               "relative_to_C64": math.sqrt(sd / sr) if sr > 0 else None,
-               "max_rel_componentwise_sampled": mrel, "rows": int(rows.numel()), "bound": 2.0 ** -16}
+        ok = math.isfinite(nw) and nw <= 2.0 ** -16
+        err = {"normwise": nw if math.isfinite(nw) else str(nw), "log2": math.log2(nw) if ok and nw > 0 else None,
+               "relative_to_C64": math.sqrt(sd / sr) if ok and sr > 0 else None,
+               "max_rel_componentwise_sampled": mrel if math.isfinite(mrel) else str(mrel),
+               "rows": int(rows.numel()), "bound": 2.0 ** -16, "ok": ok}
 
     vendor = None
     if w["kind"] == "ring" and not args.no_vendor:
@@ -641,7 +646,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"ring": "bf16" if prec != "fp32" else "f32", "strassen": "bf16",
+        "dtype": {"ring": prec if prec != "fp32" else "f32", "strassen": prec,
                   "minplus": "u32", "maxplus": "i32", "bool": "u32", "dp1d": "u32", "gap": "u32"}[w["kind"]],
         "data": "synthetic",
         "config": {"workload": args.workload, "desc": w["desc"], "precision": prec,
@@ -678,6 +683,10 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    failed = [name for name, e in (("error", err), ("server", (server or {}).get("check"))) if e and e.get("ok") is False]
+    if failed:
+        log(f"accuracy check FAILED: {failed}")
+        sys.exit(1)
     if args.hold > 0:
         t_end = time.perf_counter() + args.hold
         while time.perf_counter() < t_end:

@@ -11,7 +11,9 @@
  * ---------------------------------------
  *  - Matrices are dense and row-major.  A is n-by-k, B is k-by-m, C is
  *    n-by-m (the problem statement's orientation), each with a leading
- *    dimension (elements between rows) of at least its column count.
+ *    dimension (elements between rows) of at least its column count and
+ *    below 2^22 (PACO_ERR_UNSUPPORTED otherwise: the kernels address a
+ *    block of rows with 32-bit offsets from a 64-bit row base).
  *  - Operand and result pointers A, B, C are DEVICE pointers owned by the
  *    caller.  The library never frees them and keeps no reference past the
  *    call.  Calls are asynchronous on the context's stream: keep the buffers
@@ -115,7 +117,12 @@ typedef struct paco_ctx_s* paco_ctx;
  * from paco_graph_launch, as after a workspace change). */
 paco_status paco_create(paco_ctx* out, int device, uint64_t workspace_budget_bytes);
 paco_status paco_destroy(paco_ctx ctx);
-/* `stream` is a hipStream_t passed as an opaque pointer. */
+/* `stream` is a hipStream_t passed as an opaque pointer.  Every call of a
+ * context shares its workspace (temporary faces, Strassen temporaries), so
+ * when the stream changes, the new stream first waits (an event, no host
+ * synchronisation) for everything the context launched on the previous
+ * one: calls made through one context run in the order they were made,
+ * whichever streams they were given. */
 paco_status paco_set_stream(paco_ctx ctx, void* stream);
 /* The device's compute units.  The default processor count of a PACO call
  * is this times the number of workgroups of the chosen kernel that fit on
@@ -193,6 +200,12 @@ typedef struct paco_mm_result {
  *                   boolean kernel, overriding the chosen one (out-of-range
  *                   values are ignored). */
 paco_status paco_semiring_mm_ex(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* out);
+
+/* Host-only argument check of a descriptor: the status paco_semiring_mm_ex
+ * would return for it before touching the device (PACO_OK, or
+ * PACO_ERR_INVALID_ARG / PACO_ERR_UNSUPPORTED as documented above).
+ * Operand pointers are only tested for NULL. */
+paco_status paco_mm_validate(const paco_mm_desc* d);
 
 /* Measure the throughput of p processors (workgroups of one launch, p a
  * multiple of 8, at most 8 x compute units) for the heterogeneous split
@@ -491,7 +504,8 @@ paco_status paco_strassen_schedule(int64_t n, int32_t p, int32_t gamma, int64_t 
  *   out[0] = max |C - C64| / S   (componentwise, entries with S = 0 skipped)
  *   out[1] = max |C - C64|
  *   out[2] = sum (C - C64)^2,  out[3] = sum C64^2
- * into the host array out[4].  Dense float32 A (n-by-k), B (k-by-m),
+ * into the host array out[4].  A NaN or infinite entry of C in a sampled
+ * row counts as an infinite error (out[0] = out[1] = +infinity).  Dense float32 A (n-by-k), B (k-by-m),
  * C (n-by-m).  Synchronises the context stream. */
 paco_status paco_verify_rows_f64(paco_ctx ctx, int64_t n, int64_t m, int64_t k,
                                  const float* A, const float* B, const float* C,

@@ -63,9 +63,15 @@ typedef struct paco_server_opts {
 typedef struct paco_server_stats {
   int64_t submitted, completed, failed, batches;
   double mean_batch;            /* requests per launch */
-  double p50_s, p99_s, max_s;   /* latency done - arrival over completed */
+  double p50_s, p99_s, max_s;   /* latency done - arrival over completed
+                                   requests: p50 and p99 from a histogram of
+                                   256 bins per octave (within 0.3% of the
+                                   exact order statistic), max exact */
   double span_s;                /* first arrival to last completion */
   double ops;                   /* 2 n m k summed over completed requests */
+  int64_t retained;             /* requests the server holds (queued, in
+                                   flight, or finished and not yet polled) */
+  uint64_t bytes_in_flight;     /* admitted operand bytes not yet released */
 } paco_server_stats;
 
 /* Monotonic clock the server stamps times with (seconds). */
@@ -74,14 +80,25 @@ double paco_server_clock(void);
 paco_status paco_server_create(paco_ctx ctx, const paco_server_opts* opts, paco_server* out);
 /* Queue a request; *ticket identifies it.  Returns PACO_ERR_BUDGET when the
  * request alone exceeds the admission budget, PACO_ERR_INVALID_ARG for bad
- * shapes or pointers (nothing is queued then). */
+ * shapes or pointers, PACO_ERR_UNSUPPORTED for a leading dimension of 2^22
+ * elements or more (nothing is queued then). */
 paco_status paco_server_submit(paco_server s, const paco_request* r, uint64_t* ticket);
-/* *done = 1 and *out filled once the request has completed (or failed). */
+/* *done = 1 and *out filled once the request has completed (or failed).
+ * A request reported done is forgotten: polling its ticket again returns
+ * PACO_ERR_NOT_FOUND.  Finished requests that are never polled are kept up
+ * to 65536; beyond that the oldest are forgotten, so a long-running server
+ * holds bounded memory. */
 paco_status paco_server_poll(paco_server s, uint64_t ticket, int* done, paco_request_result* out);
 /* Block until every submitted request has completed. */
 paco_status paco_server_drain(paco_server s);
 paco_status paco_server_stats_get(paco_server s, paco_server_stats* out);
 paco_status paco_server_destroy(paco_server s);
+
+/* Testing hook for the failure path: the next `count` batches fail before
+ * any of their kernels is launched (nothing touches the device).  Their
+ * requests finish with PACO_ERR_INTERNAL and their bytes return to the
+ * admission budget; later requests run normally. */
+paco_status paco_server_fail_batches(paco_server s, int32_t count);
 
 /* Host-only: the processor split and pieces the server would launch for a
  * batch of `nreq` requests on p processors.  Pieces are written like

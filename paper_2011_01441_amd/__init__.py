@@ -168,7 +168,8 @@ class ServerStats(ctypes.Structure):
                 ("failed", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("mean_batch", ctypes.c_double), ("p50_s", ctypes.c_double),
                 ("p99_s", ctypes.c_double), ("max_s", ctypes.c_double),
-                ("span_s", ctypes.c_double), ("ops", ctypes.c_double)]
+                ("span_s", ctypes.c_double), ("ops", ctypes.c_double),
+                ("retained", ctypes.c_int64), ("bytes_in_flight", ctypes.c_uint64)]
 
 
 _lib = None
@@ -195,6 +196,7 @@ def lib():
     L.paco_last_error.restype = ctypes.c_char_p
     L.paco_semiring_mm.argtypes = [vp, i64, i64, i64, ci, vp, vp, vp]
     L.paco_semiring_mm_ex.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(MMResult)]
+    L.paco_mm_validate.argtypes = [ctypes.POINTER(MMDesc)]
     L.paco_strassen_mm.argtypes = [vp, i64, vp, vp, vp, ci, ci]
     L.paco_calibrate.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp]
     L.paco_tune.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(TuneResult)]
@@ -228,15 +230,16 @@ def lib():
     L.paco_server_drain.argtypes = [vp]
     L.paco_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
     L.paco_server_destroy.argtypes = [vp]
+    L.paco_server_fail_batches.argtypes = [vp, ctypes.c_int32]
     L.paco_batch_partition.argtypes = [ctypes.POINTER(Request), ctypes.c_int32, ctypes.c_int32,
                                        ctypes.POINTER(Piece), ctypes.POINTER(ctypes.c_int32), i64,
                                        ctypes.POINTER(i64)]
     L.paco_timing_enable.argtypes = [vp, ci]
     L.paco_timing_read.argtypes = [vp, ctypes.POINTER(Timing)]
     for name in ("paco_server_create", "paco_server_submit", "paco_server_poll",
-                 "paco_server_drain", "paco_server_stats_get", "paco_server_destroy",
+                 "paco_server_drain", "paco_server_stats_get", "paco_server_destroy", "paco_server_fail_batches",
                  "paco_batch_partition", "paco_plan_export", "paco_timing_enable", "paco_timing_read", "paco_create", "paco_destroy", "paco_set_stream", "paco_semiring_mm",
-                 "paco_semiring_mm_ex", "paco_strassen_mm", "paco_verify_rows_f64",
+                 "paco_semiring_mm_ex", "paco_mm_validate", "paco_strassen_mm", "paco_verify_rows_f64",
                  "paco_partition"):
         getattr(L, name).restype = ci
     _lib = L
@@ -718,6 +721,10 @@ class Server:
 
     def drain(self):
         _check(self._L.paco_server_drain(self._h))
+
+    def fail_batches(self, count):
+        """Testing hook: the next `count` batches fail before launch."""
+        _check(self._L.paco_server_fail_batches(self._h, count))
 
     def stats(self):
         st = ServerStats()

@@ -202,6 +202,7 @@ extern "C" paco_status paco_destroy(paco_ctx ctx) {
     (void)hipEventDestroy(mk.b);
   }
   for (hipEvent_t ev : ctx->event_pool) (void)hipEventDestroy(ev);
+  if (ctx->switch_ev) (void)hipEventDestroy(ctx->switch_ev);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->d_verify) (void)hipFree(ctx->d_verify);
   destroy_ctx_extras(ctx);
@@ -211,7 +212,16 @@ extern "C" paco_status paco_destroy(paco_ctx ctx) {
 
 extern "C" paco_status paco_set_stream(paco_ctx ctx, void* stream) {
   if (!ctx) return PACO_ERR_INVALID_ARG;
-  ctx->stream = (hipStream_t)stream;
+  hipStream_t ns = (hipStream_t)stream;
+  if (ns == ctx->stream) return PACO_OK;
+  // the workspace is shared by every call of the context: the new stream
+  // waits for what was launched on the old one
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess && !ctx->switch_ev) e = hipEventCreateWithFlags(&ctx->switch_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ctx->switch_ev, ctx->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(ns, ctx->switch_ev, 0);
+  if (e != hipSuccess) return hip_fail(ctx, e, "stream change");
+  ctx->stream = ns;
   return PACO_OK;
 }
 
@@ -564,29 +574,28 @@ std::string paco::tune_key(const paco_mm_desc* d, int prec) {
   return key;
 }
 
-paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res, int force_tile) {
-  if (res) {
-    memset(res, 0, sizeof *res);
-    res->verify_max_rel = -1;
-    res->verify_max_abs = -1;
-  }
+namespace {
+
+// Argument validation of a semiring MM descriptor (no device is touched):
+// the status the call returns for it, the reason, and the normalised sizes.
+paco_status check_desc(const paco_mm_desc* d, Norm* zo, std::string* why) {
   if (d->sr < PACO_SR_PLUS_TIMES_F32 || d->sr > PACO_SR_OR_AND_B1) {
-    set_err(ctx, "unknown semiring");
+    *why = "unknown semiring";
     return PACO_ERR_INVALID_ARG;
   }
   if (d->n < 0 || d->m < 0 || d->k < 0 || d->n >= (1ll << 31) || d->m >= (1ll << 31) ||
       d->k >= (1ll << 31)) {
-    set_err(ctx, "sizes must lie in [0, 2^31)");
+    *why = "sizes must lie in [0, 2^31)";
     return PACO_ERR_INVALID_ARG;
   }
   if (d->precision < PACO_PREC_FP32 || d->precision > PACO_PREC_AUTO || d->part < PACO_PART_PACO ||
       d->part > PACO_PART_MULTI || d->p < 0 || d->grid_split_k < 0 || d->verify_rows < 0 ||
       !(d->kcut_cost == 0 || (d->kcut_cost >= 1 && std::isfinite(d->kcut_cost)))) {
-    set_err(ctx, "invalid option");
+    *why = "invalid option";
     return PACO_ERR_INVALID_ARG;
   }
   const bool is_bool = d->sr == PACO_SR_OR_AND_B1;
-  Norm z;
+  Norm& z = *zo;
   z.sr = d->sr;
   z.n = d->n; z.m = d->m; z.k = d->k;
   z.mu = is_bool ? words(d->m) : d->m;
@@ -595,22 +604,51 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
   z.ldb = d->ldb ? d->ldb : z.mu;
   z.ldc = d->ldc ? d->ldc : z.mu;
   if (z.lda < z.ku || z.ldb < z.mu || z.ldc < z.mu) {
-    set_err(ctx, "leading dimension smaller than the row length");
+    *why = "leading dimension smaller than the row length";
     return PACO_ERR_INVALID_ARG;
   }
-  if (z.lda >= (1ll << 22) || z.ldb >= (1ll << 22)) {
-    set_err(ctx, "leading dimensions of A and B must be below 2^22 elements");
+  // the kernels form 32-bit byte offsets within a block of rows of each
+  // operand (64-bit row bases)
+  if (z.lda >= (1ll << 22) || z.ldb >= (1ll << 22) || z.ldc >= (1ll << 22)) {
+    *why = "leading dimensions of A, B and C must be below 2^22 elements";
     return PACO_ERR_UNSUPPORTED;
   }
   if (d->verify_rows > 0 && d->sr != PACO_SR_PLUS_TIMES_F32) {
-    set_err(ctx, "verify_rows applies to the ring only");
+    *why = "verify_rows applies to the ring only";
     return PACO_ERR_INVALID_ARG;
   }
   if (z.n == 0 || z.m == 0) return PACO_OK;
   if (!d->C || (z.k > 0 && (!d->A || !d->B))) {
-    set_err(ctx, "null operand");
+    *why = "null operand";
     return PACO_ERR_INVALID_ARG;
   }
+  return PACO_OK;
+}
+
+}  // namespace
+
+extern "C" paco_status paco_mm_validate(const paco_mm_desc* d) {
+  if (!d) return PACO_ERR_INVALID_ARG;
+  Norm z;
+  std::string why;
+  return check_desc(d, &z, &why);
+}
+
+paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res, int force_tile) {
+  if (res) {
+    memset(res, 0, sizeof *res);
+    res->verify_max_rel = -1;
+    res->verify_max_abs = -1;
+  }
+  Norm z;
+  std::string why;
+  paco_status vst = check_desc(d, &z, &why);
+  if (vst != PACO_OK) {
+    set_err(ctx, why);
+    return vst;
+  }
+  if (z.n == 0 || z.m == 0) return PACO_OK;
+  const bool is_bool = d->sr == PACO_SR_OR_AND_B1;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   if (z.k == 0) {

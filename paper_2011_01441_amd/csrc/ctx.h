@@ -32,6 +32,7 @@ struct DevPlan {
 struct paco_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipEvent_t switch_ev = nullptr;   // orders work across a change of stream (paco_set_stream)
   int num_cus = 0;
   std::vector<double> weights;   // processor throughputs for default-p ring calls (paco_set_processor_weights)
   struct Tuned {                 // paco_tune's choice for a shape, used by default calls

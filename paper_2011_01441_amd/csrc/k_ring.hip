@@ -340,8 +340,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
 
         // epilogue: lane holds column l32 of each 32x32 block, value 4g + r
         // in row 8g + 4*lh + r.  Stores go through a buffer resource that
-        // ends at the piece's last row, so rows past the piece are dropped by
-        // the range check; columns past it are skipped per block.
+        // starts at the block's first row (a 64-bit address, so the 32-bit
+        // offsets stay below 32 rows of the leading dimension) and ends at
+        // the piece's last row, so rows past the piece are dropped by the
+        // range check; columns past it are skipped per block.
         float* obase;
         int64_t old;
         if (W.out_off < 0) {
@@ -351,17 +353,18 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
           old = W.m1 - W.m0;
           obase = ws + W.out_off + (int64_t)(i0 - W.n0) * old - W.m0;
         }
-        const auto o_rsrc = make_rsrc(obase, W.n1 - i0, old, W.m1);
         const bool accum = W.out_off < 0 && P.accumulate;
         auto epilogue = [&](auto accum_c) {
           constexpr bool ACC = decltype(accum_c)::value;
 #pragma unroll
-          for (int a = 0; a < FM; ++a)
+          for (int a = 0; a < FM; ++a) {
+            const int r0 = wr + a * 32;
+            const auto o_rsrc = make_rsrc(obase + (int64_t)r0 * old, W.n1 - i0 - r0, old, W.m1);
 #pragma unroll
             for (int b = 0; b < FN; ++b) {
               const int c = j0 + wc + b * 32 + l32;
               if (c >= W.m1) continue;
-              const int voff = ((wr + a * 32 + 4 * lh) * (int)old + c) * 4;
+              const int voff = ((4 * lh) * (int)old + c) * 4;
 #pragma unroll
               for (int e = 0; e < 16; ++e) {
                 const int soff = (8 * (e >> 2) + (e & 3)) * (int)old * 4;
@@ -371,6 +374,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
                 __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), o_rsrc, voff, soff, 0);
               }
             }
+          }
         };
         if (accum) epilogue(std::true_type{});
         else epilogue(std::false_type{});

@@ -4,8 +4,11 @@
 // For each sampled row i and column j: C64 = sum_l A[i][l] B[l][j] and
 // S = sum_l |A[i][l] B[l][j]| in float64 (exact products of float32 values),
 // then per-block partial maxima of |C - C64| / S and |C - C64| and sums of
-// (C - C64)^2 and C64^2.  A block covers 8 sampled rows x 256 columns so B
+// (C - C64)^2 and C64^2.  A NaN or infinite entry of C counts as an
+// infinite error.  A block covers 8 sampled rows x 256 columns so B
 // is streamed once per 8 rows.
+#include <cfloat>
+
 #include "kcommon.h"
 #include "kernels.h"
 
@@ -44,7 +47,10 @@ __global__ __launch_bounds__(256) void k_verify(int64_t m, int64_t k, const floa
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
       if (ri[r] < 0) continue;
-      const double d = fabs((double)C[ri[r] * ldc + j] - acc[r]);
+      // a non-finite result (NaN or infinity in C) is an infinite error:
+      // fmax below would otherwise drop a NaN
+      double d = fabs((double)C[ri[r] * ldc + j] - acc[r]);
+      if (!(d <= DBL_MAX)) d = INFINITY;
       if (sab[r] > 0.0) mrel = fmax(mrel, d / sab[r]);
       else if (d > 0.0) mrel = INFINITY;
       mabs = fmax(mabs, d);

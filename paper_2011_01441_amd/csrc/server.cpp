@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -37,6 +38,37 @@ extern "C" double paco_server_clock(void) {
 namespace {
 
 constexpr int kSlots = 3;          // descriptor buffers (at most 2 batches in flight)
+constexpr size_t kKeepFinished = 1 << 16;   // finished, unpolled requests kept
+
+// Latency histogram: 256 bins per octave from 0.1 us (quantiles within
+// 0.3% of the exact order statistic), fixed memory whatever the count.
+struct LatHist {
+  static constexpr int kPerOct = 256;
+  static constexpr int kBins = 42 * kPerOct;   // 0.1 us .. 4.4e5 s
+  static constexpr double kMin = 1e-7;
+  std::vector<uint32_t> bins = std::vector<uint32_t>(kBins, 0);
+  uint64_t count = 0;
+  double maxv = 0.0;
+  void add(double v) {
+    int b = 0;
+    if (v > kMin) b = std::min(kBins - 1, 1 + (int)(std::log2(v / kMin) * kPerOct));
+    bins[b] += 1;
+    count += 1;
+    maxv = std::max(maxv, v);
+  }
+  // the order statistic of rank round(f (count - 1)), as the geometric
+  // centre of its bin (bin 0 reads as kMin)
+  double quantile(double f) const {
+    if (count == 0) return 0.0;
+    const uint64_t rank = std::min<uint64_t>(count - 1, (uint64_t)(f * (double)(count - 1) + 0.5));
+    uint64_t cum = 0;
+    for (int b = 0; b < kBins; ++b) {
+      cum += bins[b];
+      if (cum > rank) return b == 0 ? kMin : std::min(maxv, kMin * std::exp2((b - 0.5) / kPerOct));
+    }
+    return maxv;
+  }
+};
 
 struct ReqState {
   paco_request r;
@@ -95,7 +127,9 @@ struct paco_server_s {
   int batch_counter = 0;
   // stats
   int64_t submitted = 0, completed = 0, failed = 0, batches = 0, batched_reqs = 0;
-  std::vector<double> lat;
+  LatHist lat;
+  std::deque<uint64_t> finished_order;   // finished tickets, oldest first (retention)
+  int32_t fail_next = 0;                 // test hook: batches to fail before launch
   double first_arrival = -1, last_done = 0, ops = 0;
 
   std::thread dispatcher, completer;
@@ -330,10 +364,12 @@ void dispatcher_main(paco_server s) {
       r->res.batch_id = b.id;
       r->res.batch_size = (int32_t)rs.size();
     }
-    lk.unlock();
     // request fields read while unlocked (r, mu, ku) are never written after submit
     std::vector<paco_status> rst;
-    paco_status st = launch_batch(s, b, rs, rst);
+    const bool inject = s->fail_next > 0;   // test hook: fail this batch before any launch
+    if (inject) s->fail_next -= 1;
+    lk.unlock();
+    const paco_status st = inject ? PACO_ERR_INTERNAL : launch_batch(s, b, rs, rst);
     if (st != PACO_OK) {
       b.ok = false;
       (void)hipEventRecord(b.ev, s->main);
@@ -374,10 +410,17 @@ void completer_main(paco_server s) {
       s->pending -= 1;
       if (r.res.status == PACO_OK) {
         s->completed += 1;
-        s->lat.push_back(r.res.done_s - r.res.arrival_s);
+        s->lat.add(r.res.done_s - r.res.arrival_s);
         s->ops += 2.0 * (double)r.r.n * (double)r.r.m * (double)r.r.k;
       } else {
         s->failed += 1;
+      }
+      // bounded retention: past kKeepFinished finished requests the oldest
+      // unpolled one is forgotten
+      s->finished_order.push_back(tk);
+      if (s->finished_order.size() > kKeepFinished) {
+        s->reqs.erase(s->finished_order.front());
+        s->finished_order.pop_front();
       }
     }
     s->last_done = t;
@@ -435,9 +478,12 @@ extern "C" paco_status paco_server_submit(paco_server s, const paco_request* r, 
   const bool is_bool = r->sr == PACO_SR_OR_AND_B1;
   st.mu = is_bool ? (r->m + 31) / 32 : r->m;
   st.ku = is_bool ? (r->k + 31) / 32 : r->k;
-  if ((r->lda && r->lda < st.ku) || (r->ldb && r->ldb < st.mu) || (r->ldc && r->ldc < st.mu) ||
-      (r->lda ? r->lda : st.ku) >= (1ll << 22) || (r->ldb ? r->ldb : st.mu) >= (1ll << 22))
+  if ((r->lda && r->lda < st.ku) || (r->ldb && r->ldb < st.mu) || (r->ldc && r->ldc < st.mu))
     return PACO_ERR_INVALID_ARG;
+  // as paco_semiring_mm_ex: 32-bit offsets within a block of rows
+  if ((r->lda ? r->lda : st.ku) >= (1ll << 22) || (r->ldb ? r->ldb : st.mu) >= (1ll << 22) ||
+      (r->ldc ? r->ldc : st.mu) >= (1ll << 22))
+    return PACO_ERR_UNSUPPORTED;
   if (r->n > 0 && r->m > 0 && (!r->C || (r->k > 0 && (!r->A || !r->B)))) return PACO_ERR_INVALID_ARG;
   if (r->k == 0) return PACO_ERR_UNSUPPORTED;   // the empty fold is a plain fill: use paco_semiring_mm
   st.bytes = req_bytes(*r, st.mu, st.ku);
@@ -468,6 +514,14 @@ extern "C" paco_status paco_server_poll(paco_server s, uint64_t ticket, int* don
   if (it == s->reqs.end()) return PACO_ERR_NOT_FOUND;
   *done = it->second.finished ? 1 : 0;
   if (out) *out = it->second.res;
+  if (it->second.finished) s->reqs.erase(it);   // reported once, then forgotten
+  return PACO_OK;
+}
+
+extern "C" paco_status paco_server_fail_batches(paco_server s, int32_t count) {
+  if (!s || count < 0) return PACO_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->fail_next = count;
   return PACO_OK;
 }
 
@@ -487,14 +541,13 @@ extern "C" paco_status paco_server_stats_get(paco_server s, paco_server_stats* o
   out->failed = s->failed;
   out->batches = s->batches;
   out->mean_batch = s->batches ? (double)s->batched_reqs / (double)s->batches : 0.0;
-  std::vector<double> l = s->lat;
-  std::sort(l.begin(), l.end());
-  auto q = [&](double f) { return l.empty() ? 0.0 : l[std::min(l.size() - 1, (size_t)(f * (double)(l.size() - 1) + 0.5))]; };
-  out->p50_s = q(0.50);
-  out->p99_s = q(0.99);
-  out->max_s = l.empty() ? 0.0 : l.back();
+  out->p50_s = s->lat.quantile(0.50);
+  out->p99_s = s->lat.quantile(0.99);
+  out->max_s = s->lat.maxv;
   out->span_s = s->first_arrival >= 0 ? s->last_done - s->first_arrival : 0.0;
   out->ops = s->ops;
+  out->retained = (int64_t)s->reqs.size();
+  out->bytes_in_flight = s->bytes_in_flight;
   return PACO_OK;
 }
 

@@ -72,3 +72,38 @@ def test_create_without_device_fails_cleanly():
     h = ctypes.c_void_p()
     assert L.paco_create(ctypes.byref(h), 0, 0) != 0
     assert not h.value
+
+
+def _desc(n, m, k, sr=0, lda=0, ldb=0, ldc=0):
+    # fake non-null operand addresses: validation only tests them for NULL
+    return P.MMDesc(n, m, k, sr, 0x1000, lda, 0x2000, ldb, 0x3000, ldc, 0, 3, 0, 0, 0, 0, 0, 0.0, None)
+
+
+@pytest.mark.parametrize("sr", [0, 1, 2, 3])
+def test_leading_dimension_limits(sr):
+    # every operand's leading dimension must stay below 2^22 elements (the
+    # kernels address a block of rows with 32-bit offsets)
+    L = P.lib()
+    ok = (1 << 22) - 1
+    for lds in ((ok, 0, 0), (0, ok, 0), (0, 0, ok)):
+        assert L.paco_mm_validate(ctypes.byref(_desc(64, 64, 64, sr, *lds))) == 0
+    for lds in ((1 << 22, 0, 0), (0, 1 << 22, 0), (0, 0, 1 << 22), (0, 0, 1 << 30)):
+        assert L.paco_mm_validate(ctypes.byref(_desc(64, 64, 64, sr, *lds))) == 2   # UNSUPPORTED
+    # a leading dimension below the row length is an invalid argument
+    assert L.paco_mm_validate(ctypes.byref(_desc(64, 64, 64, sr, 0, 0, 1))) == 1
+    assert L.paco_mm_validate(None) == 1
+
+
+def test_validate_rejects_bad_descriptors():
+    L = P.lib()
+    assert L.paco_mm_validate(ctypes.byref(_desc(-1, 4, 4))) == 1
+    assert L.paco_mm_validate(ctypes.byref(_desc(4, 4, 4, sr=7))) == 1
+    d = _desc(4, 4, 4)
+    d.C = None
+    assert L.paco_mm_validate(ctypes.byref(d)) == 1
+    d = _desc(0, 4, 4)     # empty: nothing to check beyond the sizes
+    d.C = None
+    assert L.paco_mm_validate(ctypes.byref(d)) == 0
+    d = _desc(4, 4, 4, sr=1)
+    d.verify_rows = 3      # float64 verification is for the ring only
+    assert L.paco_mm_validate(ctypes.byref(d)) == 1

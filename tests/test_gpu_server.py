@@ -88,3 +88,62 @@ def test_server_small_budget_queues_and_rejects(ctx, pools):
         srv.submit(ad, bd, C, "ring")
     assert ei.value.status == 4     # PACO_ERR_BUDGET
     srv.close()
+
+
+def test_server_failed_batch_releases_budget(ctx, pools):
+    # the failure path: a batch that fails before launch fails only its own
+    # requests, returns their bytes to the admission budget, and the
+    # requests after it complete and match the oracle
+    print("case: server failed batch", flush=True)
+    srv = P.Server(ctx)
+    srv.fail_batches(1)
+    first = _run(srv, pools, SHAPES[:6])
+    st = srv.stats()
+    assert st["bytes_in_flight"] == 0
+    failed = []
+    for t, kind, n, m, k, C in first:
+        done, res = srv.poll(t)
+        assert done
+        if res["status"] != 0:
+            assert res["status"] == 6          # PACO_ERR_INTERNAL
+            failed.append(res["batch_id"])
+    assert failed and len(set(failed)) == 1    # exactly one batch failed, all of its requests
+    assert st["failed"] == len(failed) and st["completed"] == 6 - len(failed)
+    later = _run(srv, pools, SHAPES[6:14])
+    _check(pools, srv, later)
+    st = srv.stats()
+    assert st["failed"] == len(failed) and st["completed"] == 14 - len(failed)
+    assert st["bytes_in_flight"] == 0 and st["retained"] == 0
+    srv.close()
+
+
+def test_server_forgets_polled_requests(ctx, pools):
+    # memory stays bounded: a request is dropped once it is reported done,
+    # and the latency statistics live in a fixed-size histogram
+    print("case: server retention", flush=True)
+    srv = P.Server(ctx)
+    a, b, ad, bd = pools["minplus"]
+    C = torch.empty((8, 8), dtype=ad.dtype, device=DEV)
+    lat = []
+    for rnd in range(4):
+        ts = [srv.submit(ad[:8, :8], bd[:8, :8], C, "minplus") for _ in range(500)]
+        srv.drain()
+        assert srv.stats()["retained"] == 500
+        for t in ts:
+            done, res = srv.poll(t)
+            assert done and res["status"] == 0
+            lat.append(res["done_s"] - res["arrival_s"])
+        st = srv.stats()
+        assert st["retained"] == 0
+        with pytest.raises(P.PacoError) as ei:
+            srv.poll(ts[0])
+        assert ei.value.status == 7            # PACO_ERR_NOT_FOUND
+    st = srv.stats()
+    assert st["completed"] == 2000
+    lat = np.sort(np.array(lat))
+    for q, key in ((0.5, "p50_s"), (0.99, "p99_s")):
+        exact = lat[min(len(lat) - 1, int(q * (len(lat) - 1) + 0.5))]
+        assert abs(st[key] - exact) <= 0.003 * exact + 1e-7, (key, st[key], exact)
+    assert st["max_s"] == pytest.approx(lat[-1])
+    assert np.array_equal(C.cpu().numpy(), oracle.minplus(a[:8, :8], b[:8, :8]))
+    srv.close()
