@@ -201,6 +201,28 @@ typedef struct paco_mm_result {
  *                   values are ignored). */
 paco_status paco_semiring_mm_ex(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* out);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * call as paco_semiring_mm_ex (same plan, same kernels, bit-identical
+ * results), except that it calls no hipMalloc, hipFree or other allocating
+ * routine: the plan's device tables and the temporary faces of its k-cuts
+ * are placed in one fixed device array of PACO_NOALLOC_SCRATCH_BYTES
+ * (64 MiB), which every device the library runs on holds from the first
+ * paco_create on that device until the process ends.  Each call first
+ * copies the plan's tables (kept in host memory, cached per shape by the
+ * context) into that array on the context's stream, then launches.
+ *  - A plan whose tables and faces exceed the array returns PACO_ERR_BUDGET
+ *    without launching anything (raise kcut_cost for fewer k-cuts).
+ *  - verify_rows > 0 returns PACO_ERR_UNSUPPORTED.
+ *  - Every call on one device shares that device's array, and the array
+ *    keeps the last call's contents: calls that overlap on one device
+ *    (different streams or contexts without ordering between them) race and
+ *    give wrong results.  Calls on one stream are ordered. */
+#define PACO_NOALLOC_SCRATCH_BYTES (64ull << 20)
+paco_status paco_semiring_mm_noalloc(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* out);
+/* PACO_NOALLOC_SCRATCH_BYTES as the library was built with. */
+uint64_t paco_noalloc_scratch_bytes(void);
+
 /* Host-only argument check of a descriptor: the status paco_semiring_mm_ex
  * would return for it before touching the device (PACO_OK, or
  * PACO_ERR_INVALID_ARG / PACO_ERR_UNSUPPORTED as documented above).

@@ -197,6 +197,9 @@ def lib():
     L.paco_semiring_mm.argtypes = [vp, i64, i64, i64, ci, vp, vp, vp]
     L.paco_semiring_mm_ex.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(MMResult)]
     L.paco_mm_validate.argtypes = [ctypes.POINTER(MMDesc)]
+    L.paco_semiring_mm_noalloc.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(MMResult)]
+    L.paco_noalloc_scratch_bytes.argtypes = []
+    L.paco_noalloc_scratch_bytes.restype = ctypes.c_uint64
     L.paco_strassen_mm.argtypes = [vp, i64, vp, vp, vp, ci, ci]
     L.paco_calibrate.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp]
     L.paco_tune.argtypes = [vp, ctypes.POINTER(MMDesc), ctypes.POINTER(TuneResult)]
@@ -239,7 +242,7 @@ def lib():
     for name in ("paco_server_create", "paco_server_submit", "paco_server_poll",
                  "paco_server_drain", "paco_server_stats_get", "paco_server_destroy", "paco_server_fail_batches",
                  "paco_batch_partition", "paco_plan_export", "paco_timing_enable", "paco_timing_read", "paco_create", "paco_destroy", "paco_set_stream", "paco_semiring_mm",
-                 "paco_semiring_mm_ex", "paco_mm_validate", "paco_strassen_mm", "paco_verify_rows_f64",
+                 "paco_semiring_mm_ex", "paco_semiring_mm_noalloc", "paco_mm_validate", "paco_strassen_mm", "paco_verify_rows_f64",
                  "paco_partition"):
         getattr(L, name).restype = ci
     _lib = L
@@ -473,11 +476,21 @@ class Context:
                    ctypes.c_void_p(w.ctypes.data) if w is not None else None)
         return d, w
 
-    def semiring_mm(self, A, B, semiring="ring", *, n=None, m=None, k=None, C=None,
-                    accumulate=False, precision="auto", part="paco", p=0, split_k=0,
-                    verify_rows=0, verify_seed=0, kcut_cost=0.0, weights=None, return_result=False):
+    def semiring_mm(self, A, B, semiring="ring", **kw):
         """C = A (x) B.  Boolean operands are bit-packed int32 words; pass
         their logical sizes n, m, k.  Returns C (and a result dict)."""
+        return self._mm(self._L.paco_semiring_mm_ex, A, B, semiring, **kw)
+
+    def semiring_mm_noalloc(self, A, B, semiring="ring", **kw):
+        """As semiring_mm, through the entry point that allocates no device
+        memory (paco_semiring_mm_noalloc): C must be given."""
+        if kw.get("C") is None:
+            raise ValueError("the allocation-free call needs its output buffer C")
+        return self._mm(self._L.paco_semiring_mm_noalloc, A, B, semiring, **kw)
+
+    def _mm(self, fn, A, B, semiring="ring", *, n=None, m=None, k=None, C=None,
+            accumulate=False, precision="auto", part="paco", p=0, split_k=0,
+            verify_rows=0, verify_seed=0, kcut_cost=0.0, weights=None, return_result=False):
         sr = SEMIRING[semiring]
         dt = _DTYPE[sr]
         self._check_tensor(A, "A", dt)
@@ -508,7 +521,7 @@ class Context:
                    ctypes.c_void_p(w.ctypes.data) if w is not None else None)
         r = MMResult()
         self._stream()
-        _check(self._L.paco_semiring_mm_ex(self._h, ctypes.byref(d), ctypes.byref(r)), self._h)
+        _check(fn(self._h, ctypes.byref(d), ctypes.byref(r)), self._h)
         if not return_result:
             return C
         res = {f[0]: getattr(r, f[0]) for f in MMResult._fields_}

@@ -188,6 +188,10 @@ extern "C" paco_status paco_create(paco_ctx* out, int device, uint64_t budget) {
   c->device = device;
   c->num_cus = prop.multiProcessorCount;
   c->budget = budget ? budget : (64ull << 30);
+  if (noalloc_init(c) != PACO_OK) {
+    delete c;
+    return PACO_ERR_HIP;
+  }
   *out = c;
   return PACO_OK;
 }
@@ -627,6 +631,31 @@ paco_status check_desc(const paco_mm_desc* d, Norm* zo, std::string* why) {
 
 }  // namespace
 
+namespace paco {
+
+// Lays the plan's device tables out in one host block (each table 256-byte
+// aligned) and places the temporary faces after it.
+void pack_tables(HostTables* t) {
+  const HostPlan& h = t->plan.h;
+  auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+  t->items_off = 0;
+  t->wg_off = al(t->items_off + h.items.size() * sizeof(WorkItem));
+  t->tiles_off = al(t->wg_off + h.wg_off.size() * sizeof(int32_t));
+  t->srcs_off = al(t->tiles_off + h.tiles.size() * sizeof(RedTile));
+  const uint64_t end = t->srcs_off + h.srcs.size() * sizeof(RedSrc);
+  t->faces_off = al(end);
+  t->blob.assign(end, 0);
+  auto put = [&](uint64_t off, const void* src, size_t bytes) {
+    if (bytes) memcpy(t->blob.data() + off, src, bytes);
+  };
+  put(t->items_off, h.items.data(), h.items.size() * sizeof(WorkItem));
+  put(t->wg_off, h.wg_off.data(), h.wg_off.size() * sizeof(int32_t));
+  put(t->tiles_off, h.tiles.data(), h.tiles.size() * sizeof(RedTile));
+  put(t->srcs_off, h.srcs.data(), h.srcs.size() * sizeof(RedSrc));
+}
+
+}  // namespace paco
+
 extern "C" paco_status paco_mm_validate(const paco_mm_desc* d) {
   if (!d) return PACO_ERR_INVALID_ARG;
   Norm z;
@@ -634,7 +663,8 @@ extern "C" paco_status paco_mm_validate(const paco_mm_desc* d) {
   return check_desc(d, &z, &why);
 }
 
-paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res, int force_tile) {
+paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res, int force_tile,
+                         const FixedScratch* fx) {
   if (res) {
     memset(res, 0, sizeof *res);
     res->verify_max_rel = -1;
@@ -646,6 +676,10 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
   if (vst != PACO_OK) {
     set_err(ctx, why);
     return vst;
+  }
+  if (fx && d->verify_rows > 0) {
+    set_err(ctx, "verify_rows needs device buffers of its own: use paco_semiring_mm_ex");
+    return PACO_ERR_UNSUPPORTED;
   }
   if (z.n == 0 || z.m == 0) return PACO_OK;
   const bool is_bool = d->sr == PACO_SR_OR_AND_B1;
@@ -714,23 +748,77 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
            (long long)z.m, (long long)z.k, part, p, d->grid_split_k, z.prec, kc, tenv ? tenv : "",
            (unsigned long long)whash, force_tile);
   DevPlan* dp = nullptr;
-  auto itp = ctx->plans.find(key);
-  if (itp != ctx->plans.end()) {
-    dp = itp->second.get();
-  } else {
-    trim_plans(ctx);
-    std::unique_ptr<DevPlan> np(new DevPlan());
-    make_mm_plan((int)d->sr, z.n, z.m, z.k, part, p, d->grid_split_k, z.prec, ctx->num_cus, np.get(), kc, weights,
-                 force_tile);
-    paco_status st = upload_plan(ctx, np.get());
+  // device tables of the plan and the temporary faces: the plan's own
+  // allocations and the context's workspace, or (fx) the caller's fixed
+  // scratch, into which the host copies of the tables are written
+  const WorkItem* d_items = nullptr;
+  const int32_t* d_wg_off = nullptr;
+  const RedTile* d_tiles = nullptr;
+  const RedSrc* d_srcs = nullptr;
+  void* ws = nullptr;
+  paco_status st = PACO_OK;
+  if (!fx) {
+    auto itp = ctx->plans.find(key);
+    if (itp != ctx->plans.end()) {
+      dp = itp->second.get();
+    } else {
+      trim_plans(ctx);
+      std::unique_ptr<DevPlan> np(new DevPlan());
+      make_mm_plan((int)d->sr, z.n, z.m, z.k, part, p, d->grid_split_k, z.prec, ctx->num_cus, np.get(), kc,
+                   weights, force_tile);
+      st = upload_plan(ctx, np.get());
+      if (st != PACO_OK) return st;
+      dp = np.get();
+      ctx->plans[key] = std::move(np);
+    }
+    // ---- workspace
+    st = ensure_ws(ctx, (uint64_t)dp->h.temp_elems * 4);
     if (st != PACO_OK) return st;
-    dp = np.get();
-    ctx->plans[key] = std::move(np);
+    d_items = dp->d_items;
+    d_wg_off = dp->d_wg_off;
+    d_tiles = dp->d_tiles;
+    d_srcs = dp->d_srcs;
+    ws = ctx->ws;
+  } else {
+    auto itp = ctx->host_plans.find(key);
+    HostTables* ht = nullptr;
+    if (itp != ctx->host_plans.end()) {
+      ht = itp->second.get();
+    } else {
+      if (ctx->host_plans.size() >= PACO_PLAN_CACHE_MAX) {
+        // a copy from one of these host tables may still be pending
+        if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_fail(ctx, e, "plan cache sync");
+        ctx->host_plans.clear();
+      }
+      std::unique_ptr<HostTables> nt(new HostTables());
+      make_mm_plan((int)d->sr, z.n, z.m, z.k, part, p, d->grid_split_k, z.prec, ctx->num_cus, &nt->plan, kc,
+                   weights, force_tile);
+      pack_tables(nt.get());
+      ht = nt.get();
+      ctx->host_plans[key] = std::move(nt);
+    }
+    dp = &ht->plan;
+    const uint64_t need = ht->faces_off + (uint64_t)dp->h.temp_elems * 4;
+    if (need > fx->bytes) {
+      char buf[256];
+      snprintf(buf, sizeof buf,
+               "the plan needs %llu bytes of scratch (tables and %lld temporary-face elements); the fixed "
+               "scratch holds %llu: use paco_semiring_mm_ex, or a partition with fewer k-cuts (kcut_cost)",
+               (unsigned long long)need, (long long)dp->h.temp_elems, (unsigned long long)fx->bytes);
+      set_err(ctx, buf);
+      return PACO_ERR_BUDGET;
+    }
+    char* base = (char*)fx->ptr;
+    if (!ht->blob.empty() &&
+        (e = hipMemcpyAsync(base, ht->blob.data(), ht->blob.size(), hipMemcpyHostToDevice, ctx->stream)) !=
+            hipSuccess)
+      return hip_fail(ctx, e, "plan table copy");
+    d_items = (const WorkItem*)(base + ht->items_off);
+    d_wg_off = (const int32_t*)(base + ht->wg_off);
+    d_tiles = (const RedTile*)(base + ht->tiles_off);
+    d_srcs = (const RedSrc*)(base + ht->srcs_off);
+    ws = base + ht->faces_off;
   }
-
-  // ---- workspace
-  paco_status st = ensure_ws(ctx, (uint64_t)dp->h.temp_elems * 4);
-  if (st != PACO_OK) return st;
 
   // ---- launch
   ProbRef pr;
@@ -743,21 +831,19 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
   {
   TimeScope ts(ctx, 0);
   if (dp->fam == 0)
-    e = launch_semiring_int((int)d->sr, dp->tile, pr, dp->d_items, dp->d_wg_off, dp->h.nwg,
-                            dp->h.xcd_remap, ctx->ws, ctx->stream);
+    e = launch_semiring_int((int)d->sr, dp->tile, pr, d_items, d_wg_off, dp->h.nwg, dp->h.xcd_remap, ws,
+                            ctx->stream);
   else if (dp->fam == 1)
-    e = launch_semiring_bool(dp->tile, pr, dp->d_items, dp->d_wg_off, dp->h.nwg, dp->h.xcd_remap,
-                             ctx->ws, ctx->stream);
+    e = launch_semiring_bool(dp->tile, pr, d_items, d_wg_off, dp->h.nwg, dp->h.xcd_remap, ws, ctx->stream);
   else
-    e = launch_ring(z.prec, dp->tile, pr, dp->d_items, dp->d_wg_off, dp->h.nwg, dp->h.xcd_remap,
-                    ctx->ws, ctx->stream);
+    e = launch_ring(z.prec, dp->tile, pr, d_items, d_wg_off, dp->h.nwg, dp->h.xcd_remap, ws, ctx->stream);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "semiring kernel launch");
   if (!dp->h.tiles.empty()) {
     TimeScope ts(ctx, 1);
     const int rvec = (dp->h.red_vec == 4 && (uintptr_t)d->C % 16 == 0 && z.ldc % 4 == 0) ? 4 : 1;
-    e = launch_reduce(is_bool ? SR_BOOL : (int)d->sr, pr, dp->d_tiles, (int)dp->h.tiles.size(),
-                      dp->d_srcs, ctx->ws, ctx->stream, rvec);
+    e = launch_reduce(is_bool ? SR_BOOL : (int)d->sr, pr, d_tiles, (int)dp->h.tiles.size(), d_srcs, ws,
+                      ctx->stream, rvec);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");
   }
   if (res) {

@@ -27,6 +27,21 @@ struct DevPlan {
   virtual ~DevPlan();
 };
 
+// A plan whose device tables are not allocated: one host block holding the
+// tables (copied to fixed scratch memory at each call) and the offsets of
+// each table and of the temporary faces in that memory.
+struct HostTables {
+  DevPlan plan;   // device pointers stay null
+  std::vector<unsigned char> blob;
+  uint64_t items_off = 0, wg_off = 0, tiles_off = 0, srcs_off = 0, faces_off = 0;
+};
+
+// Caller-provided device memory for a call that allocates nothing.
+struct FixedScratch {
+  void* ptr;
+  uint64_t bytes;
+};
+
 }  // namespace paco
 
 struct paco_ctx_s {
@@ -52,6 +67,7 @@ struct paco_ctx_s {
   int64_t* d_rows = nullptr;
   int64_t rows_cap = 0;
   std::map<std::string, std::unique_ptr<paco::DevPlan>> plans;
+  std::map<std::string, std::unique_ptr<paco::HostTables>> host_plans;   // paco_semiring_mm_noalloc
   std::string last_error;
   // per-kernel timing (paco_timing_enable)
   bool timing = false;
@@ -89,7 +105,14 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
 double default_kcut_cost(int sr);
 double plan_kcut_cost(int sr);
 // The semiring MM call; force_tile >= 0 fixes the kernel tile (tuning).
-paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res, int force_tile = -1);
+// With fx, the plan's tables and temporary faces go to that memory and the
+// call allocates no device memory (PACO_ERR_BUDGET when they do not fit).
+paco_status run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* res, int force_tile = -1,
+                   const FixedScratch* fx = nullptr);
+void pack_tables(HostTables* t);
+// Per-device address of the fixed scratch array (noalloc.cpp); called by
+// paco_create with the device current.
+paco_status noalloc_init(paco_ctx ctx);
 // key of paco_tune's choices
 std::string tune_key(const paco_mm_desc* d, int prec);
 
