@@ -402,6 +402,156 @@ def bench_server(torch, P, count, rate, check=32):
     return out
 
 
+def piece_balance(torch, ctx, w, Ad, Bd, C, **kw):
+    """Device-side record of one call: when each processor (workgroup)
+    started and finished its work, on the 100 MHz device clock, and which
+    compute unit it ran on.  Returns duration statistics per processor and
+    per compute unit (several grid workgroups can share one)."""
+    cap = 65536
+    st = torch.full((cap, 4), -1, dtype=torch.int64, device=Ad.device)
+    ctx.set_piece_stamps(st)
+    try:
+        for _ in range(3):
+            _, r = call(ctx, w, Ad, Bd, C, return_result=True, **kw)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_piece_stamps(None)
+    s = st.cpu().numpy()
+    s = s[s[:, 0] >= 0]
+    s = s[: r["p"]] if len(s) >= r["p"] else s
+    t0, t1 = s[:, 0].astype(np.float64), s[:, 1].astype(np.float64)
+    dur = (t1 - t0) / 100.0                      # microseconds
+    span = (t1.max() - t0.min()) / 100.0
+    # compute unit: XCC_ID plus the CU / shader-array / engine fields of HW_ID
+    cu_key = s[:, 2] * 256 + ((s[:, 3] >> 8) & 0xFF)
+    keys, inv = np.unique(cu_key, return_inverse=True)
+    per_cu = np.bincount(inv, weights=dur)
+    xcc = np.bincount(s[:, 2].astype(np.int64) & 0xF, weights=dur, minlength=8)
+
+    def st_(v):
+        return {"max_us": round(float(v.max()), 2), "mean_us": round(float(v.mean()), 2),
+                "min_us": round(float(v.min()), 2), "max_over_mean": round(float(v.max() / v.mean()), 4)}
+
+    return {"processors": int(len(s)), "compute_units": int(len(keys)), "call_span_us": round(span, 2),
+            "processor": st_(dur), "compute_unit_busy": st_(per_cu),
+            "finish_spread_us": round(float((t1.max() - t1.min()) / 100.0), 2),
+            "busy_fraction": round(float(per_cu.sum() / (len(keys) * span)), 4),
+            "busy_us_per_xcc": [round(float(x), 1) for x in xcc[:8]]}
+
+
+# The other configurations of the benchmark suite, summarised beside the
+# headline line: (label, workload).  C4 is the request server.
+CONFIG_SET = [("C0", "minplus_c0"), ("C2a", "maxplus_c2a"), ("C2b", "bool_c2b"),
+              ("minplus_8192", "minplus_8192"), ("C3", "strassen_c3_levels2"), ("C3_pbfs", "strassen_c3")]
+
+
+def config_summary(torch, P, ctx, label, name, steps):
+    """One configuration: PACO step time, the dominant kernel's roofline
+    fraction, the autotuned tile grid (or, for Strassen, the classic product)
+    on the same operands, and a parity verdict against the oracle (integer
+    semirings: bit-exact on every output row, or on sampled rows for the
+    8192^3 shape; Strassen: float64 normwise error of sampled rows)."""
+    import oracle
+    w = WORKLOADS[name]
+    dev = torch.device("cuda:0")
+    t_start = time.perf_counter()
+    A, B, Ad, Bd = make_inputs(w, torch, dev)
+    prec = w.get("prec", "int")
+    if w["kind"] == "bool":
+        C = torch.empty((w["n"], (w["m"] + 31) // 32), dtype=torch.int32, device=dev)
+    elif w["kind"] == "strassen":
+        C = torch.empty((w["n"], w["n"]), dtype=torch.float32, device=dev)
+    else:
+        C = torch.empty((w["n"], w["m"]), dtype=Ad.dtype, device=dev)
+    one = timed(torch, lambda: call(ctx, w, Ad, Bd, C), 1)
+    for _ in range(max(3, min(2000, int(math.ceil(0.2 / max(one, 1e-6)))))):
+        call(ctx, w, Ad, Bd, C)
+    ms = timed(torch, lambda: call(ctx, w, Ad, Bd, C), steps) * 1e3
+    ctx.timing(True)
+    timed(torch, lambda: call(ctx, w, Ad, Bd, C), steps)
+    tm = ctx.timing()
+    ctx.timing(False)
+    kern_ms = tm["main_ms"] / max(tm["launches"], 1)
+    work, unit, bound, peak = algorithmic(w, prec)
+    achieved = work / (kern_ms * 1e-3) / 1e12
+    out = {"workload": name, "desc": w["desc"], "ms_per_step": round(ms, 4),
+           "value": round(classic_ops(w) / (ms * 1e-3) / 1e9, 3), "unit": "GOP/s",
+           "roofline": {"kernel": {"strassen": "k_ring", "minplus": "k_semiring_int", "maxplus": "k_semiring_int",
+                                   "bool": "k_semiring_bool"}[w["kind"]],
+                        "bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                        "frac": round(achieved / peak, 4), "kernel_ms": round(kern_ms, 4),
+                        "kernel_launches_per_step": round(tm["launches"] / steps, 2),
+                        "reduce_ms": round(tm["reduce_ms"] / steps, 4),
+                        "other_ms": round(tm["other_ms"] / steps, 4)}}
+    if w["kind"] == "strassen":
+        f = (lambda: ctx.semiring_mm(Ad, Bd, "ring", C=C, precision=w["prec"]))
+        for _ in range(3):
+            f()
+        cms = timed(torch, f, steps) * 1e3
+        out["classic_ms"] = round(cms, 4)
+        out["strassen_vs_classic"] = round(cms / ms, 4)
+    else:
+        tile_env = {"bool": "PACO_BOOL_TILE"}.get(w["kind"], "PACO_INT_TILE")
+        best = None
+        for tile in (0, 1, 2, 3):
+            os.environ[tile_env] = str(tile)
+            for sk in (1, 2, 4, 8, 16, 32, 64):
+                f = (lambda sk=sk: call(ctx, w, Ad, Bd, C, part="grid", split_k=sk))
+                f()
+                t = timed(torch, f, 2) * 1e3
+                if best is None or t < best[2]:
+                    best = (tile, sk, t)
+        os.environ[tile_env] = str(best[0])
+        gms = timed(torch, lambda: call(ctx, w, Ad, Bd, C, part="grid", split_k=best[1]), steps) * 1e3
+        del os.environ[tile_env]
+        out["grid_ms"] = round(gms, 4)
+        out["grid_tile_split_k"] = [best[0], best[1]]
+        out["paco_vs_grid"] = round(gms / ms, 4)
+        if ms < 0.1:   # launch-bound: the same step replayed from a hipGraph
+            rep = 50
+            G = (ctx.graph(Ad, Bd, "bool", n=w["n"], m=w["m"], k=w["k"], C=C, repeat=rep) if w["kind"] == "bool"
+                 else ctx.graph(Ad, Bd, w["kind"], C=C, repeat=rep))
+            for _ in range(2):
+                G.launch()
+            out["graph_replay_ms"] = round(timed(torch, G.launch, 1) * 1e3 / rep, 4)
+            G.close()
+    # parity of the PACO result
+    call(ctx, w, Ad, Bd, C)
+    torch.cuda.synchronize()
+    if w["kind"] == "strassen":
+        rows = torch.arange(0, w["n"], max(1, w["n"] // 64), device=dev)
+        mrel, mabs, sd, sr = ctx.verify_rows(Ad, Bd, C, rows)
+        na = float(np.linalg.norm(A.astype(np.float64)))
+        nb = float(np.linalg.norm(B.astype(np.float64)))
+        nw = math.sqrt(sd * w["n"] / rows.numel()) / (na * nb)
+        ok = math.isfinite(nw) and nw <= 2.0 ** -16
+        out["parity"] = {"check": "float64 normwise ||C - C64||_F / (||A||_F ||B||_F) from sampled rows",
+                         "rows": int(rows.numel()), "normwise": nw if math.isfinite(nw) else str(nw),
+                         "log2": math.log2(nw) if ok and nw > 0 else None,
+                         "max_rel_componentwise_sampled": mrel if math.isfinite(mrel) else str(mrel),
+                         "bound": 2.0 ** -16, "ok": ok}
+    else:
+        n = w["n"]
+        rows = np.arange(n) if name != "minplus_8192" else np.unique(
+            np.concatenate([np.linspace(0, n - 1, 30).astype(np.int64), [0, n - 1]]))
+        got = C.cpu().numpy()[rows]
+        if w["kind"] == "minplus":
+            ref = oracle.minplus(A[rows], B)
+        elif w["kind"] == "maxplus":
+            ref = oracle.maxplus(A[rows], B)
+        else:
+            ref = oracle.bool_packed(A[rows].view(np.uint32), B.view(np.uint32), rows.size, w["m"], w["k"])
+            got = got.view(np.uint32)
+        bad = int(np.count_nonzero(got != ref))
+        out["parity"] = {"check": "bit-exact against the oracle", "rows": int(rows.size), "of_rows": n,
+                         "mismatches": bad, "ok": bad == 0}
+    out["seconds"] = round(time.perf_counter() - t_start, 1)
+    log(f"config {label} ({name}): {json.dumps(out)}")
+    del A, B, Ad, Bd, C
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -427,6 +577,11 @@ def main():
                          "(for sampling clocks and power from outside)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (calibrates HBM byte counters)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the summary of the other configurations (C0, C2a, C2b, (min,+) 8192^3, C3)")
+    ap.add_argument("--config-steps", type=int, default=10)
+    ap.add_argument("--balance", action="store_true",
+                    help="record per-processor start/end times on the device (PACO and the tuned grid)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -578,6 +733,16 @@ def main():
                 "tile": best[0], "split_k": best[1]}
         log(f"grid: {gms:.3f} ms/step (tile {best[0]}, split_k {best[1]})")
 
+    balance = None
+    if args.balance and w["kind"] in ("ring", "minplus", "maxplus", "bool"):
+        balance = {"paco": piece_balance(torch, ctx, w, Ad, Bd, C)}
+        if grid is not None:
+            tile_env = {"ring": "PACO_RING_TILE", "bool": "PACO_BOOL_TILE"}.get(w["kind"], "PACO_INT_TILE")
+            os.environ[tile_env] = str(grid["tile"])
+            balance["grid"] = piece_balance(torch, ctx, w, Ad, Bd, C, part="grid", split_k=grid["split_k"])
+            del os.environ[tile_env]
+        log(f"balance: {json.dumps(balance)}")
+
     # ---- accuracy of this result
     err = None
     if w["kind"] == "gap":
@@ -630,6 +795,13 @@ def main():
     if not args.no_server:
         server = bench_server(torch, P, args.server_requests, 2000.0)
 
+    configs = None
+    if not args.no_configs and args.workload == "ring_longk":
+        cctx = P.Context(0)   # a context of its own, without the ring's processor weights
+        configs = {label: config_summary(torch, P, cctx, label, name, args.config_steps)
+                   for label, name in CONFIG_SET}
+        cctx.close()
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, A, B, args.cpu_seconds)
@@ -680,10 +852,14 @@ def main():
         "strassen_vs_classic": round(classic["ms_per_step"] / ms, 4) if classic else None,
         "error": err,
         "server": server,
+        "configs": configs,
+        "balance": balance,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    failed = [name for name, e in (("error", err), ("server", (server or {}).get("check"))) if e and e.get("ok") is False]
+    checks = [("error", err), ("server", (server or {}).get("check"))]
+    checks += [(f"config {label}", c["parity"]) for label, c in (configs or {}).items()]
+    failed = [name for name, e in checks if e and e.get("ok") is False]
     if failed:
         log(f"accuracy check FAILED: {failed}")
         sys.exit(1)

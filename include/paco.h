@@ -129,6 +129,18 @@ paco_status paco_set_stream(paco_ctx ctx, void* stream);
  * one compute unit at once (1 for the matrix-core ring kernel, 2-4 for the
  * VALU kernels); paco_mm_result.p reports the value used. */
 int paco_num_cus(paco_ctx ctx);
+/* Device-side balance record (section "PACO Design and Analysis": every
+ * processor should finish at the same time).  With `stamps` set (a DEVICE
+ * buffer of 4 * capacity uint64 words, owned by the caller), each later
+ * semiring MM call of this context (paco_semiring_mm, _ex, _noalloc) has
+ * the workgroup standing for processor q < capacity write, at
+ * stamps[4q .. 4q+3]: the start and the end of its work, on the device's
+ * 100 MHz real-time counter, and the XCC_ID and HW_ID hardware registers of
+ * where it ran (processors of a GRID call are its output tiles).  Slots of
+ * processors the call does not have keep their old contents.  Each kernel
+ * adds one barrier per processor while it is set.  NULL (capacity 0) turns
+ * it off.  Strassen and server calls record nothing. */
+paco_status paco_set_piece_stamps(paco_ctx ctx, void* stamps, int32_t capacity);
 const char* paco_status_string(paco_status s);
 const char* paco_last_error(paco_ctx ctx);
 

@@ -189,6 +189,8 @@ def lib():
     L.paco_destroy.argtypes = [vp]
     L.paco_set_stream.argtypes = [vp, vp]
     L.paco_num_cus.argtypes = [vp]
+    L.paco_set_piece_stamps.argtypes = [vp, vp, ctypes.c_int32]
+    L.paco_set_piece_stamps.restype = ci
     L.paco_num_cus.restype = ci
     L.paco_status_string.argtypes = [ci]
     L.paco_status_string.restype = ctypes.c_char_p
@@ -388,6 +390,20 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_piece_stamps(self, stamps=None):
+        """stamps: an int64 device tensor of shape (P, 4), or None.  Later
+        semiring MM calls record, per processor q < P: start and end of its
+        work (100 MHz device clock), XCC_ID and HW_ID registers."""
+        if stamps is None:
+            _check(self._L.paco_set_piece_stamps(self._h, None, 0), self._h)
+            self._stamps = None
+            return
+        if (stamps.dtype != torch.int64 or stamps.dim() != 2 or stamps.shape[1] != 4 or not stamps.is_contiguous()
+                or stamps.device.type != "cuda"):
+            raise ValueError("stamps must be a contiguous int64 (P, 4) device tensor")
+        _check(self._L.paco_set_piece_stamps(self._h, _ptr(stamps), stamps.shape[0]), self._h)
+        self._stamps = stamps   # kept alive while set
 
     @property
     def num_cus(self):

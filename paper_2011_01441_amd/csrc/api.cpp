@@ -231,6 +231,13 @@ extern "C" paco_status paco_set_stream(paco_ctx ctx, void* stream) {
 
 extern "C" int paco_num_cus(paco_ctx ctx) { return ctx ? ctx->num_cus : 0; }
 
+extern "C" paco_status paco_set_piece_stamps(paco_ctx ctx, void* stamps, int32_t capacity) {
+  if (!ctx || capacity < 0 || (stamps && capacity == 0)) return PACO_ERR_INVALID_ARG;
+  ctx->stamps = (uint64_t*)stamps;
+  ctx->stamp_cap = stamps ? capacity : 0;
+  return PACO_OK;
+}
+
 extern "C" const char* paco_status_string(paco_status s) {
   switch (s) {
     case PACO_OK: return "ok";
@@ -828,6 +835,8 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
   pr.base.n = (int32_t)z.n; pr.base.m = (int32_t)z.m; pr.base.k = (int32_t)z.k;
   pr.base.accumulate = d->accumulate ? 1 : 0;
   pr.vec_ok = ring_vec_ok(d->A, z.lda, d->B, z.ldb, z.m, z.k) ? 1 : 0;
+  pr.stamps = ctx->stamps;
+  pr.stamp_cap = ctx->stamps ? ctx->stamp_cap : 0;
   {
   TimeScope ts(ctx, 0);
   if (dp->fam == 0)

@@ -49,6 +49,8 @@ struct paco_ctx_s {
   hipStream_t stream = nullptr;
   hipEvent_t switch_ev = nullptr;   // orders work across a change of stream (paco_set_stream)
   int num_cus = 0;
+  uint64_t* stamps = nullptr;    // paco_set_piece_stamps: per-processor timestamps of semiring MM calls
+  int32_t stamp_cap = 0;
   std::vector<double> weights;   // processor throughputs for default-p ring calls (paco_set_processor_weights)
   struct Tuned {                 // paco_tune's choice for a shape, used by default calls
     int part = 0, p = 0, tile = -1;

@@ -39,7 +39,10 @@ struct ProbRef {
   int32_t vec_ok;      // set by the host: every problem's A and B rows are
                        // 16-byte aligned with lengths multiple of 4 (the
                        // ring kernel may use 128-bit loads)
-  int32_t pad;
+  int32_t stamp_cap;   // processors with a slot in `stamps`
+  uint64_t* stamps;    // null, or 4 words per processor: start and end of
+                       // its work on the device's 100 MHz clock, its XCC_ID
+                       // and HW_ID hardware registers
 };
 
 // A sub-cuboid [n0,n1) x [m0,m1) x [k0,k1) of problem `prob`.  out_off < 0:

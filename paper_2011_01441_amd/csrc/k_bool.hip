@@ -50,6 +50,7 @@ __global__ __launch_bounds__(kThreads) void k_semiring_bool(ProbRef pr, const Wo
   const int tx = t % TX, ty = t / TX;
   const int q = remap_wg(blockIdx.x, nwg, xcd);
   const int it1 = wg_off[q + 1];
+  stamp_start(pr, q);
   int buf = 0;
   for (int it = wg_off[q]; it < it1; ++it) {
     const WorkItem W = uni(items[it]);
@@ -149,6 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_semiring_bool(ProbRef pr, const Wo
       }
     }
   }
+  stamp_end(pr, q);
 }
 
 }  // namespace

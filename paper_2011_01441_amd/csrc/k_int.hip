@@ -67,6 +67,7 @@ __global__ __launch_bounds__(kThreads) void k_semiring_int(ProbRef pr, const Wor
   const int tx = t % TX, ty = t / TX;
   const int q = remap_wg(blockIdx.x, nwg, xcd);
   const int it1 = wg_off[q + 1];
+  stamp_start(pr, q);
   int buf = 0;
   for (int it = wg_off[q]; it < it1; ++it) {
     const WorkItem W = uni(items[it]);
@@ -169,6 +170,7 @@ __global__ __launch_bounds__(kThreads) void k_semiring_int(ProbRef pr, const Wor
       }
     }
   }
+  stamp_end(pr, q);
 }
 
 template <class Op>

@@ -123,6 +123,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
   const int l32 = lane & 31, lh = lane >> 5;                   // row/col in block, k-half
   const int q = remap_wg(blockIdx.x, nwg, xcd);
   const int it1 = wg_off[q + 1];
+  stamp_start(pr, q);
 
   for (int it = wg_off[q]; it < it1; ++it) {
     const WorkItem W = uni(items[it]);
@@ -381,6 +382,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
       }
     }
   }
+  stamp_end(pr, q);
 }
 
 template <int PREC, int BM, int BN, int WM, int WN>

@@ -80,4 +80,26 @@ __device__ __forceinline__ void gstore(T* p, T v) {
   *(__attribute__((address_space(1))) T*)p = v;
 }
 
+// Per-processor timestamps (off unless the host gave a buffer): the
+// workgroup standing for processor q records when it starts and ends its
+// work on the real-time counter (100 MHz, one clock for the device) and
+// the XCC_ID / HW_ID registers that name the die and compute unit it ran on.
+// The end is taken after a barrier, once every wave is done.
+constexpr int kHwRegHwId = 4 | (31 << 11);    // s_getreg encoding: HW_ID, 32 bits
+constexpr int kHwRegXccId = 20 | (15 << 11);  // XCC_ID, 16 bits
+__device__ __forceinline__ void stamp_start(const ProbRef& pr, int q) {
+  if (pr.stamps && q < pr.stamp_cap && threadIdx.x == 0) {
+    uint64_t* s = pr.stamps + 4 * (int64_t)q;
+    gstore(s, (uint64_t)__builtin_amdgcn_s_memrealtime());
+    gstore(s + 2, (uint64_t)(uint32_t)__builtin_amdgcn_s_getreg(kHwRegXccId));
+    gstore(s + 3, (uint64_t)(uint32_t)__builtin_amdgcn_s_getreg(kHwRegHwId));
+  }
+}
+__device__ __forceinline__ void stamp_end(const ProbRef& pr, int q) {
+  if (pr.stamps && q < pr.stamp_cap) {
+    __syncthreads();
+    if (threadIdx.x == 0) gstore(pr.stamps + 4 * (int64_t)q + 1, (uint64_t)__builtin_amdgcn_s_memrealtime());
+  }
+}
+
 }  // namespace paco

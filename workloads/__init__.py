@@ -56,11 +56,32 @@ def words(seed, stream, count, offset=0):
     return _mix(z)
 
 
-def _chunked(fn, seed, stream, count, dtype, chunk=1 << 24):
+_CHUNK = 1 << 22   # even, so Box-Muller pairs never straddle two chunks
+
+
+def _parallel(job, count, chunk=_CHUNK):
+    """Run job(start, length) over [0, count) in chunks, on a few threads
+    (numpy releases the interpreter lock in its array loops).  Chunks are
+    independent: the generator is counter-based."""
+    starts = list(range(0, count, chunk))
+    if len(starts) <= 1:
+        for s in starts:
+            job(s, min(chunk, count - s))
+        return
+    import concurrent.futures as cf
+    import os
+    workers = max(1, min(16, len(os.sched_getaffinity(0)), len(starts)))
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(lambda s: job(s, min(chunk, count - s)), starts))
+
+
+def _chunked(fn, seed, stream, count, dtype):
     out = np.empty(count, dtype)
-    for s in range(0, count, chunk):
-        c = min(chunk, count - s)
+
+    def job(s, c):
         out[s:s + c] = fn(words(seed, stream, c, s))
+
+    _parallel(job, count)
     return out
 
 
@@ -98,11 +119,11 @@ def normal_f32(seed, stream, shape):
         return z[: w.size].astype(np.float32)
 
     out = np.empty(count, np.float32)
-    chunk = 1 << 24
-    for s in range(0, count, chunk):
-        c = min(chunk, count - s)
-        ww = words(seed, stream, c + (c % 2), s)
-        out[s:s + c] = fn(ww)[:c]
+
+    def job(s, c):
+        out[s:s + c] = fn(words(seed, stream, c + (c % 2), s))[:c]
+
+    _parallel(job, count)
     return out.reshape(shape)
 
 
