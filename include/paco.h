@@ -139,7 +139,8 @@ int paco_num_cus(paco_ctx ctx);
  * where it ran (processors of a GRID call are its output tiles).  Slots of
  * processors the call does not have keep their old contents.  Each kernel
  * adds one barrier per processor while it is set.  NULL (capacity 0) turns
- * it off.  Strassen and server calls record nothing. */
+ * it off.  paco_strassen_mm records its batched leaf product; the pruned-BFS
+ * Strassen and server calls record nothing. */
 paco_status paco_set_piece_stamps(paco_ctx ctx, void* stamps, int32_t capacity);
 const char* paco_status_string(paco_status s);
 const char* paco_last_error(paco_ctx ctx);
@@ -583,6 +584,11 @@ typedef struct paco_part_opts {
   int32_t max_rounds;        /* multi-piece: after this many rounds of p
                                 pieces hand out the rest round-robin
                                 (0 = divide down to the quanta) */
+  int32_t tile_balance;      /* MM-1-Piece only; 1: the quanta are a kernel's
+                                tile sides, and a cut that cannot land evenly
+                                on them gives way to a nearly as long
+                                dimension that can (how the ring product
+                                plans its pieces); 0: the paper's rule */
 } paco_part_opts;
 
 /* Host-only.  Partition the n-by-m-by-k cuboid over opts->p processors.

@@ -138,7 +138,7 @@ class PartOpts(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("q_n", ctypes.c_int32), ("q_m", ctypes.c_int32),
                 ("q_k", ctypes.c_int32), ("weights", ctypes.POINTER(ctypes.c_double)),
                 ("multi_piece", ctypes.c_int32), ("kcut_cost", ctypes.c_double),
-                ("max_rounds", ctypes.c_int32)]
+                ("max_rounds", ctypes.c_int32), ("tile_balance", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -308,11 +308,13 @@ def gap_plan(m, n, part="paco", p=1024, min_piece=65536):
     return la[:int(info[0])], bl[:int(info[1])], pc[:int(info[2])], int(info[3])
 
 
-def partition(n, m, k, p, q=(1, 1, 1), weights=None, multi_piece=False, kcut_cost=1.0, max_rounds=0):
+def partition(n, m, k, p, q=(1, 1, 1), weights=None, multi_piece=False, kcut_cost=1.0, max_rounds=0,
+              tile_balance=False):
     """Host-only PACO partition (MM-1-Piece, or pruned-BFS multi-piece):
     a list of dicts with n0,n1,m0,m1,k0,k1, proc, temp, round, depth."""
     L = lib()
-    o = PartOpts(p, q[0], q[1], q[2], None, 1 if multi_piece else 0, kcut_cost, max_rounds)
+    o = PartOpts(p, q[0], q[1], q[2], None, 1 if multi_piece else 0, kcut_cost, max_rounds,
+                 1 if tile_balance else 0)
     if weights is not None:
         arr = (ctypes.c_double * p)(*[float(w) for w in weights])
         o.weights = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))

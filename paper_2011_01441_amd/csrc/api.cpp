@@ -271,6 +271,7 @@ extern "C" paco_status paco_partition(int64_t n, int64_t m, int64_t k, const pac
   po.kcut_cost = o->kcut_cost > 0 ? o->kcut_cost : 1.0;
   if (!(po.kcut_cost >= 1.0) || !std::isfinite(po.kcut_cost) || o->max_rounds < 0) return PACO_ERR_INVALID_ARG;
   po.max_rounds = o->max_rounds;
+  po.tile_balance = o->tile_balance != 0;
   if (o->weights)
     for (int i = 0; i < o->p; ++i)
       if (!(o->weights[i] > 0) || !std::isfinite(o->weights[i])) return PACO_ERR_INVALID_ARG;
@@ -355,6 +356,55 @@ static int env_tile(const char* name, int count, int dflt) {
   if (!v) return dflt;
   int t = atoi(v);
   return (t >= 0 && t < count) ? t : dflt;
+}
+
+// MM-1-Piece of a ring product on the matrix-core kernel's tile grid: for
+// each tile shape the cuts of n and m land on whole tiles (when the
+// dimension holds two), k on the 32-deep step, with the tile-balanced
+// dimension choice; the tile whose busiest processor has the least padded
+// work (weighted by the tile's measured relative cost, plus a prologue and
+// epilogue of two steps per tile) wins.  force_tile >= 0 tries that one only.
+std::vector<Piece> ring_partition(int64_t n, int64_t m, int64_t k, int p, int prec, double kcut_cost,
+                                  const double* weights, int force_tile, int* tile_out) {
+  const int cand[4] = {RING_T256x256, RING_T256x128, RING_T128x128, RING_T128x64};
+  const double eff[4] = {1.0, 1.1, 1.25, 1.6};
+  const double k_ovh = 64.0;
+  std::vector<Piece> best;
+  double bestc = 1e300;
+  int bt = -1;
+  for (int c = 0; c < 4; ++c) {
+    const int t = cand[c];
+    if (force_tile >= 0 && t != force_tile) continue;
+    if (t == RING_T256x256 && prec == PREC_BF16X6 && force_tile < 0) continue;   // three parts do not fit
+    const RingTileShape ts = ring_tile_shape(t, prec);
+    PartOpts po;
+    po.p = p;
+    po.kcut_cost = kcut_cost;
+    po.weights = weights;
+    po.q[0] = n >= 2 * ts.tm ? ts.tm : 16;
+    po.q[1] = m >= 2 * ts.tn ? ts.tn : 16;
+    po.q[2] = ts.bk;
+    po.tile_balance = true;
+    po.tile_n = ts.tm;
+    po.tile_m = ts.tn;
+    po.tile_k_ovh = k_ovh;
+    std::vector<Piece> v = partition_mm1(n, m, k, po);
+    double worst = 0;
+    for (const Piece& pc : v) {
+      if (pc.empty()) continue;
+      const double tiles = (double)((pc.n1 - pc.n0 + ts.tm - 1) / ts.tm) * (double)((pc.m1 - pc.m0 + ts.tn - 1) / ts.tn);
+      const double kk = (double)((pc.k1 - pc.k0 + ts.bk - 1) / ts.bk * ts.bk);
+      const double w = weights ? weights[pc.proc] : 1.0;
+      worst = std::max(worst, tiles * ts.tm * ts.tn * (kk + k_ovh) * eff[c] / w);
+    }
+    if (worst < bestc) {
+      bestc = worst;
+      best = std::move(v);
+      bt = t;
+    }
+  }
+  *tile_out = bt;
+  return best;
 }
 
 // Host part of a semiring MM plan: partition, tile choice, work lists.
@@ -456,6 +506,12 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
           }
         }
       }
+    } else if (fam == 2 && part == PACO_PART_PACO) {
+      if (p <= 0) p = num_cus;
+      if (kcut_cost <= 0) kcut_cost = 1.0;
+      kcut_cost_used = kcut_cost;
+      const int forced = force_tile >= 0 ? force_tile : env_tile(tile_env, 5, -1);
+      pcs = ring_partition(n, m, k, p, prec, kcut_cost, weights, forced, &tile);
     } else {
       if (p <= 0) p = num_cus;
       if (kcut_cost <= 0) po.kcut_cost = 1.0;

@@ -94,6 +94,8 @@ paco_status ensure_ws(paco_ctx ctx, uint64_t bytes);
 int choose_int_tile(const std::vector<Piece>& pcs);
 int choose_bool_tile(const std::vector<Piece>& pcs);
 int choose_ring_tile(const std::vector<Piece>& pcs, int prec);
+std::vector<Piece> ring_partition(int64_t n, int64_t m, int64_t k, int p, int prec, double kcut_cost,
+                                  const double* weights, int force_tile, int* tile_out);
 paco_status verify_sampled(paco_ctx ctx, int64_t n, int64_t m, int64_t k, const float* A, int64_t lda,
                            const float* B, int64_t ldb, const float* C, int64_t ldc, int rows,
                            uint64_t seed, paco_mm_result* res);

@@ -18,11 +18,17 @@
 // of a per-dimension quantum, rounded to nearest; a dimension shorter than
 // two quanta is not cut while another one can be.  An optional k-cut cost
 // divides k's virtual length in that choice (1 keeps the paper's rule).
+// On a kernel's tile grid (tile_balance) the quanta are whole tiles and
+// the dimension of each ratio cut is searched for (TileSearch below): the
+// paper's bounds assume cuts at any position, while a tile kernel pads
+// every partial tile, and the padding of one uneven cut compounds down the
+// tree.
 #include "partition.h"
 
 #include <algorithm>
 #include <cmath>
 #include <deque>
+#include <map>
 
 namespace paco {
 
@@ -75,11 +81,11 @@ void mm1_rec(const Box& b, const double v[3], int p0, int p1, int depth, const P
     out.push_back(make_piece(b, p0, 0, depth));
     return;
   }
-  int d = pick_dim(v, b, o.q, o.kcut_cost);
   int pl = P / 2;
   double wl = wprefix[p0 + pl] - wprefix[p0];
   double wa = wprefix[p1] - wprefix[p0];
   double f = wa > 0 ? wl / wa : (double)pl / (double)P;
+  int d = pick_dim(v, b, o.q, o.kcut_cost);
   int64_t c = cut_offset(b.len(d), f, o.q[d]);
   Box l = b, r = b;
   l.hi[d] = b.lo[d] + c;
@@ -90,6 +96,95 @@ void mm1_rec(const Box& b, const double v[3], int p0, int p1, int depth, const P
   mm1_rec(r, vh, p0 + pl, p1, depth + 1, o, wprefix, out);
 }
 
+// MM-1-Piece on a tile grid.  The recursion is the paper's (cut in the
+// processor ratio, recurse on both halves), but the cut dimension is found
+// by a search: cost(box, P, face) is the busiest processor's cost below
+// the box, min over cuttable dimensions of max(cost(left), cost(right)).
+// Cut positions depend only on the lengths and P, so the search is memoised
+// on (lengths, P, whether the box starts above k = 0, i.e. writes faces).
+// Ties (within 0.1%) keep the paper's choice.  Processor weights make each
+// subrange's ratio differ, so the search is keyed on the first processor
+// too.
+struct TileSearch {
+  const PartOpts& o;
+  const std::vector<double>& wprefix;
+  int64_t tn, tm;
+  struct Key {
+    int64_t len[3];
+    int p0, P;
+    bool face;
+    bool operator<(const Key& b) const {
+      if (len[0] != b.len[0]) return len[0] < b.len[0];
+      if (len[1] != b.len[1]) return len[1] < b.len[1];
+      if (len[2] != b.len[2]) return len[2] < b.len[2];
+      if (p0 != b.p0) return p0 < b.p0;
+      if (P != b.P) return P < b.P;
+      return face < b.face;
+    }
+  };
+  std::map<Key, std::pair<double, int>> memo;
+
+  double leaf(const int64_t len[3], bool face, int p0) const {
+    if (len[0] <= 0 || len[1] <= 0 || len[2] <= 0) return 0.0;
+    const double tiles = (double)((len[0] + tn - 1) / tn) * (double)((len[1] + tm - 1) / tm);
+    const double kk = (double)((len[2] + o.q[2] - 1) / o.q[2] * o.q[2]);
+    const double w = o.weights ? o.weights[p0] : 1.0;
+    return tiles * (double)tn * (double)tm * (kk + o.tile_k_ovh + (face ? o.tile_face : 0.0)) / w;
+  }
+  double frac(int p0, int P) const {
+    const int pl = P / 2;
+    const double wl = wprefix[p0 + pl] - wprefix[p0], wa = wprefix[p0 + P] - wprefix[p0];
+    return wa > 0 ? wl / wa : (double)pl / (double)P;
+  }
+  // (cost, dimension) of the best cut of a box with these lengths
+  std::pair<double, int> solve(const int64_t len[3], const double v[3], int p0, int P, bool face) {
+    if (P == 1) return {leaf(len, face, p0), -1};
+    Key key{{len[0], len[1], len[2]}, o.weights ? p0 : 0, P, face};
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+    Box b{{0, 0, 0}, {len[0], len[1], len[2]}};
+    const int d0 = pick_dim(v, b, o.q, o.kcut_cost);
+    const double f = frac(p0, P);
+    const int pl = P / 2;
+    std::pair<double, int> best{1e300, d0};
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int d = 0; d < 3; ++d) {
+        if ((pass == 0) != (d == d0)) continue;   // the paper's choice first
+        if (d != d0 && len[d] < 2 * o.q[d]) continue;
+        const int64_t c = cut_offset(len[d], f, o.q[d]);
+        int64_t ll[3] = {len[0], len[1], len[2]}, lr[3] = {len[0], len[1], len[2]};
+        ll[d] = c;
+        lr[d] = len[d] - c;
+        double vh[3] = {v[0], v[1], v[2]};
+        vh[d] = v[d] / 2.0;
+        const double cl = solve(ll, vh, p0, pl, face).first;
+        const double cr = solve(lr, vh, p0 + pl, P - pl, face || (d == 2 && c > 0)).first;
+        const double cst = std::max(cl, cr);
+        if (cst < best.first * (1.0 - 1e-3)) best = {cst, d};
+      }
+    }
+    memo[key] = best;
+    return best;
+  }
+  void build(const Box& b, const double v[3], int p0, int P, int depth, std::vector<Piece>& out) {
+    if (P == 1) {
+      out.push_back(make_piece(b, p0, 0, depth));
+      return;
+    }
+    const int64_t len[3] = {b.len(0), b.len(1), b.len(2)};
+    const int d = solve(len, v, p0, P, b.lo[2] > 0).second;
+    const int pl = P / 2;
+    const int64_t c = cut_offset(b.len(d), frac(p0, P), o.q[d]);
+    Box l = b, r = b;
+    l.hi[d] = b.lo[d] + c;
+    r.lo[d] = b.lo[d] + c;
+    double vh[3] = {v[0], v[1], v[2]};
+    vh[d] = v[d] / 2.0;
+    build(l, vh, p0, pl, depth + 1, out);
+    build(r, vh, p0 + pl, P - pl, depth + 1, out);
+  }
+};
+
 }  // namespace
 
 std::vector<Piece> partition_mm1(int64_t n, int64_t m, int64_t k, const PartOpts& o) {
@@ -99,6 +194,11 @@ std::vector<Piece> partition_mm1(int64_t n, int64_t m, int64_t k, const PartOpts
   for (int i = 0; i < o.p; ++i) wprefix[i + 1] = wprefix[i] + (o.weights ? o.weights[i] : 1.0);
   Box b{{0, 0, 0}, {n, m, k}};
   double v[3] = {(double)n, (double)m, (double)k};
+  if (o.tile_balance) {
+    TileSearch ts{o, wprefix, o.tile_n > 0 ? o.tile_n : o.q[0], o.tile_m > 0 ? o.tile_m : o.q[1], {}};
+    ts.build(b, v, 0, o.p, 0, out);
+    return out;
+  }
   mm1_rec(b, v, 0, o.p, 0, o, wprefix, out);
   return out;
 }

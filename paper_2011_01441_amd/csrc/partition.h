@@ -24,6 +24,16 @@ struct PartOpts {
   // multi-piece: rounds of p pieces before the rest goes out round-robin
   // (0 = none; division then stops at the quanta)
   int max_rounds = 0;
+  // MM-1-Piece on a kernel's tile grid (see partition.cpp): cuts still
+  // split each cuboid in the processor ratio, on the quanta, but the
+  // dimension of each cut is chosen to minimise the busiest processor's
+  // cost: its output tiles (tile_n x tile_m, 0 = the quanta) times its
+  // k-range padded to q[2], plus a per-tile overhead of tile_k_ovh and, for
+  // a piece that writes a temporary face, tile_face (both in units of k)
+  bool tile_balance = false;
+  int64_t tile_n = 0, tile_m = 0;
+  double tile_k_ovh = 64.0;
+  double tile_face = 128.0;
 };
 
 // MM-1-Piece (corollary mm-1-piece): exactly p pieces, piece j on proc j.

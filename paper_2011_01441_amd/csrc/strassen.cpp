@@ -101,27 +101,54 @@ extern "C" paco_status paco_strassen_mm(paco_ctx ctx, int64_t n, const float* A,
   } else {
     trim_plans(ctx);
     std::unique_ptr<DevPlan> np(new DevPlan());
-    PartOpts po;
-    po.p = p;
-    po.q[0] = 16; po.q[1] = 16; po.q[2] = 32;
-    po.kcut_cost = default_kcut_cost(PACO_SR_PLUS_TIMES_F32);
-    std::vector<Piece> pcs = partition_mm1((int64_t)nleaf * h, h, h, po);
+    // Two schedules of the 7^L leaf products.  Sequenced: one leaf split
+    // over all p processors (MM-1-Piece on the tile grid), processor q
+    // running its piece of every leaf, leaf after leaf, so all processors
+    // work on the same leaf at a time and its S and T blocks stay in the
+    // last-level cache.  Stacked: the leaves concatenated along n and split
+    // as one product, pieces straddling leaves; each piece then streams its
+    // own leaves' T blocks, and every row tile re-reads its column panel.
+    // Sequenced is taken unless its busiest processor has over 2% more
+    // padded work than the stacked one's.
+    const double kc = default_kcut_cost(PACO_SR_PLUS_TIMES_F32);
+    auto crit = [&](const std::vector<Piece>& v, int t, double mult) {
+      const RingTileShape ts = ring_tile_shape(t, prec);
+      std::vector<double> load(p, 0.0);
+      double worst = 0;
+      for (const Piece& pc : v) {
+        if (pc.empty()) continue;
+        load[pc.proc] += mult * (double)((pc.n1 - pc.n0 + ts.tm - 1) / ts.tm) *
+                         (double)((pc.m1 - pc.m0 + ts.tn - 1) / ts.tn) * ts.tm * ts.tn *
+                         (double)((pc.k1 - pc.k0 + ts.bk - 1) / ts.bk * ts.bk + 64);
+        worst = std::max(worst, load[pc.proc]);
+      }
+      return worst;
+    };
+    int tile_seq = -1, tile_stk = -1;
+    std::vector<Piece> one = ring_partition(h, h, h, p, prec, kc, nullptr, -1, &tile_seq);
+    std::vector<Piece> pcs = ring_partition((int64_t)nleaf * h, h, h, p, prec, kc, nullptr, -1, &tile_stk);
     std::vector<TaggedPiece> tp;
-    std::vector<Piece> local;
-    for (const Piece& pc : pcs) {
-      if (pc.empty()) continue;
-      for (int64_t r = pc.n0 / h; r * h < pc.n1; ++r) {
-        Piece q = pc;
-        q.n0 = std::max(pc.n0, r * h) - r * h;
-        q.n1 = std::min(pc.n1, (r + 1) * h) - r * h;
-        if (q.n1 <= q.n0) continue;
-        tp.push_back({q, (int32_t)r, pc.proc});
-        local.push_back(q);
+    int tile = tile_stk;
+    if (crit(one, tile_seq, (double)nleaf) <= 1.02 * crit(pcs, tile_stk, 1.0)) {
+      tile = tile_seq;
+      for (int r = 0; r < nleaf; ++r)
+        for (const Piece& pc : one)
+          if (!pc.empty()) tp.push_back({pc, (int32_t)r, pc.proc});
+    } else {
+      for (const Piece& pc : pcs) {
+        if (pc.empty()) continue;
+        for (int64_t r = pc.n0 / h; r * h < pc.n1; ++r) {
+          Piece q = pc;
+          q.n0 = std::max(pc.n0, r * h) - r * h;
+          q.n1 = std::min(pc.n1, (r + 1) * h) - r * h;
+          if (q.n1 <= q.n0) continue;
+          tp.push_back({q, (int32_t)r, pc.proc});
+        }
       }
     }
     std::vector<ProbGeom> geom(nleaf, ProbGeom{h, h, h});
     np->h = build_plan(tp, p, true, geom);
-    np->tile = choose_ring_tile(local, prec);
+    np->tile = tile;
     np->fam = 2;
     np->p = p;
     paco_status st = upload_plan(ctx, np.get());
@@ -151,6 +178,8 @@ extern "C" paco_status paco_strassen_mm(paco_ctx ctx, int64_t n, const float* A,
   pr.base.n = pr.base.m = pr.base.k = (int32_t)h;
   pr.sA = pr.sB = pr.sC = (int64_t)blk;
   pr.vec_ok = (h % 4 == 0) ? 1 : 0;   // S, T blocks start 16-byte aligned when h % 4 == 0
+  pr.stamps = ctx->stamps;
+  pr.stamp_cap = ctx->stamps ? ctx->stamp_cap : 0;
   {
     TimeScope ts(ctx, 0);
     e = launch_ring(prec, dp->tile, pr, dp->d_items, dp->d_wg_off, dp->h.nwg, dp->h.xcd_remap, ctx->ws,

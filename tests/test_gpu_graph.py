@@ -96,11 +96,12 @@ def test_stale_graph_is_refused():
         A, B = workloads.minplus_operands(384, 256, 320, seed=25)
         Cg = torch.empty((384, 256), dtype=torch.int32, device=DEV)
         g = c.graph(dev(A), dev(B), "minplus", C=Cg)
-        # a call with far larger temporary faces (the paper's k-cut rule on a
-        # long k: 255 faces of 1024 x 1024) grows and so reallocates the workspace
-        X = torch.randn(1024, 131072, device=DEV)
-        Y = torch.randn(131072, 1024, device=DEV)
-        _, r = c.semiring_mm(X, Y, "ring", precision="bf16x3", kcut_cost=1.0, return_result=True)
+        # a call with far larger temporary faces (1024 processors on a long k:
+        # 16 output tiles, each cut 64-way in k) grows and so reallocates the
+        # workspace
+        X = torch.randn(1024, 65536, device=DEV)
+        Y = torch.randn(65536, 1024, device=DEV)
+        _, r = c.semiring_mm(X, Y, "ring", precision="bf16x3", p=1024, return_result=True)
         assert r["temp_elems"] * 4 > 64 << 20
         torch.cuda.synchronize()
         with pytest.raises(Exception):

@@ -89,26 +89,81 @@ def test_ring_plan_replay_small_integers(n, m, k, p):
     np.testing.assert_array_equal(C, oracle.ring_i64(A.astype(np.int64), B.astype(np.int64)))
 
 
-def test_plan_sizes_match_paper_shapes(monkeypatch):
+def test_plan_sizes_match_paper_shapes():
     # long k: (2048, 1024, 65536) on 256 processors -> 512 x 1024 x 1024 pieces,
     # k cut 64-way: 252 temporary faces (4 n-blocks x 63) under the paper's
     # longest-dimension rule (k-cut cost 1)
-    monkeypatch.setenv("PACO_KCUT_COST", "1")
-    items, wg, tiles, srcs, info = P.plan_export(2048, 1024, 65536, "ring", p=256,
-                                                 precision="bf16x3")
-    ext = items[:, [2, 4, 6]] - items[:, [1, 3, 5]]
+    pcs = P.partition(2048, 1024, 65536, 256, q=(16, 16, 32), kcut_cost=1.0)
+    ext = np.array([[p["n1"] - p["n0"], p["m1"] - p["m0"], p["k1"] - p["k0"]] for p in pcs])
     assert (ext == [512, 1024, 1024]).all()
-    assert (items[:, 7] >= 0).sum() == 252
-    assert info["xcd_remap"] == 1 and info["n_wg"] == 256
+    assert sum(p["temp"] for p in pcs) == 252
 
 
-def test_ring_default_kcut_cost_prefers_n_and_m_cuts():
-    # the ring path's default k-cut cost (16): k is cut only while it is more
-    # than 16 times longer than n and m -> 256 x 256 x 8192 pieces on (2048,
-    # 1024, 65536)
-    items, *_ = P.plan_export(2048, 1024, 65536, "ring", p=256, precision="bf16x3")
+def test_ring_plan_long_k_pieces():
+    # the ring plan on the 256 x 256 tile grid: every processor gets one
+    # output tile 8192 deep (k cut 8-way: 224 faces); the first three cuts
+    # go to the eight dies in groups of 32 consecutive processors
+    items, wg, tiles, srcs, info = P.plan_export(2048, 1024, 65536, "ring", p=256, precision="bf16x3")
     ext = items[:, [2, 4, 6]] - items[:, [1, 3, 5]]
     assert (ext == [256, 256, 8192]).all()
+    assert (items[:, 7] >= 0).sum() == 224
+    assert info["xcd_remap"] == 1 and info["n_wg"] == 256 and info["tile"] == 4
+
+
+RING_TILE = {0: (256, 128), 1: (128, 128), 2: (128, 64), 3: (128, 128), 4: (256, 256)}
+
+
+def padded_critical(items, wg, info, k_ovh=64):
+    """Busiest workgroup's padded work (whole tiles x k-range on the 32-deep
+    step, plus two steps of overhead per tile) over the even share."""
+    tm, tn = RING_TILE[info["tile"]]
+    worst = 0
+    for q in range(info["n_wg"]):
+        w = 0
+        for i in range(wg[q], wg[q + 1]):
+            _, n0, n1, m0, m1, k0, k1, _ = items[i]
+            w += -(-(n1 - n0) // tm) * tm * -(-(m1 - m0) // tn) * tn * (-(-(k1 - k0) // 32) * 32 + k_ovh)
+        worst = max(worst, w)
+    return worst
+
+
+@pytest.mark.parametrize("n,m,k,p,bound", [(2048, 1024, 65536, 251, 1.06), (2048, 1024, 65536, 200, 1.06),
+                                           (2048, 1024, 65536, 97, 1.03), (200704, 4096, 4096, 256, 1.02),
+                                           (8192, 8192, 8192, 200, 1.06)])
+def test_ring_plan_tile_balance(n, m, k, p, bound):
+    """Arbitrary (also prime) p on the tile grid: the busiest processor's
+    padded work stays within a few percent of n m k / p, where cuts of n and
+    m rounded to whole tiles alone would pad whole tile rows (the batched
+    Strassen leaves (49 x 4096, 4096, 4096) over 256 processors leave
+    3.06 row tiles per processor)."""
+    items, wg, _, _, info = P.plan_export(n, m, k, "ring", p=p, precision="bf16x3")
+    assert info["n_wg"] == p
+    assert padded_critical(items, wg, info) <= bound * n * m * k / p
+
+
+@pytest.mark.parametrize("n,m,k", [(2048, 1024, 65536), (8192, 8192, 8192), (3000, 2000, 5000), (700, 900, 33000)])
+@pytest.mark.parametrize("p", [7, 97, 128, 200, 251, 256])
+def test_tile_search_never_worse_than_paper_rule(n, m, k, p):
+    """The tile-grid search picks each cut's dimension among all of them,
+    the paper's choice included, so its busiest processor (same quanta, same
+    cost: whole 256 x 256 tiles, k on the 32-step, two steps per tile, four
+    more for a piece that writes a face) is never worse than under the
+    paper's longest-dimension rule."""
+    def cost(pcs):
+        w = {}
+        for pc in pcs:
+            t = -(-(pc["n1"] - pc["n0"]) // 256) * -(-(pc["m1"] - pc["m0"]) // 256)
+            kk = -(-(pc["k1"] - pc["k0"]) // 32) * 32
+            if pc["n1"] > pc["n0"] and pc["m1"] > pc["m0"] and kk > 0:
+                w[pc["proc"]] = w.get(pc["proc"], 0) + t * (kk + 64 + (128 if pc["k0"] > 0 else 0))
+        return max(w.values())
+    q = (256 if n >= 512 else 16, 256 if m >= 512 else 16, 32)
+    paper = P.partition(n, m, k, p, q=q, kcut_cost=16.0)
+    tiled = P.partition(n, m, k, p, q=q, kcut_cost=16.0, tile_balance=True)
+    assert sorted(pc["proc"] for pc in tiled) == list(range(p))
+    vol = sum((pc["n1"] - pc["n0"]) * (pc["m1"] - pc["m0"]) * (pc["k1"] - pc["k0"]) for pc in tiled)
+    assert vol == n * m * k
+    assert cost(tiled) <= cost(paper) * (1 + 1e-9)
 
 
 @pytest.mark.parametrize("sr,n,m,k", [("minplus", 384, 256, 320), ("minplus", 700, 300, 2048),

@@ -120,12 +120,12 @@ def test_noalloc_rejects_oversized_plan(ctx):
     ctx._stream()
     cap = L.paco_noalloc_scratch_bytes()
     assert cap == 64 << 20
-    n, m, k = 1024, 1024, 65536   # 64 k-slices of 4 MiB faces at kcut_cost 1
+    n, m, k = 1024, 1024, 65536   # 1024 processors: 16 tiles cut 64-way in k, 252 MiB of faces
     print(f"case: noalloc oversized ring {n}x{m}x{k}", flush=True)
     A = torch.zeros((n, k), dtype=torch.float32, device=DEV)
     B = torch.zeros((k, m), dtype=torch.float32, device=DEV)
     C = torch.full((n, m), 3.0, dtype=torch.float32, device=DEV)
-    d = desc("ring", n, m, k, A, B, C, precision="bf16x3", kcut_cost=1.0)
+    d = desc("ring", n, m, k, A, B, C, precision="bf16x3", p=1024)
     r = P.MMResult()
     st = L.paco_semiring_mm_noalloc(ctx._h, ctypes.byref(d), ctypes.byref(r))
     assert st == ERR_BUDGET
