@@ -211,7 +211,12 @@ typedef struct paco_mm_result {
  *   PACO_RING_TILE, PACO_INT_TILE, PACO_BOOL_TILE
  *                   index of the tile shape of the ring, (min,+)/(max,+) or
  *                   boolean kernel, overriding the chosen one (out-of-range
- *                   values are ignored). */
+ *                   values are ignored);
+ *   PACO_FUSE_FOLD  1: the product kernel folds the temporary faces of
+ *                   k-cuts itself (the last piece to finish a reduction
+ *                   cell folds it, same order and results), 2: only when
+ *                   every cell is small, 0 (default): a second launch folds
+ *                   them (measured faster on this device). */
 paco_status paco_semiring_mm_ex(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* out);
 
 /* For callers that cannot allocate device memory: code under HIP graph
@@ -620,12 +625,24 @@ typedef struct paco_plan_info {
   int32_t n_wg, n_items, n_tiles, n_srcs;
   int32_t tile, red_vec, xcd_remap;
   int64_t temp_elems;
+  int32_t fused;                /* 1: the product kernel folds the temporary
+                                   faces (each tile is one reduction cell,
+                                   folded by the last piece covering it to
+                                   finish); 0: a separate fold launch */
+  int32_t n_fold_list;          /* fused: entries of the item -> cell lists */
 } paco_plan_info;
 
 paco_status paco_plan_export(int64_t n, int64_t m, int64_t k, paco_semiring sr, paco_part_mode part,
                              int32_t p, int32_t split_k, paco_precision prec, int32_t num_cus,
                              paco_plan_info* info, int64_t* items, int32_t* wg_off, int32_t* tiles,
                              int64_t* srcs);
+/* Host-only: the fused-fold tables of the same plan (info as above): per
+ * tile the number of pieces covering the cell (pads[n_tiles]); per item the
+ * (begin, count) of the cells it covers in fold_list (item_fold[2 n_items],
+ * fold_list[n_fold_list]).  NULL arrays fill info only. */
+paco_status paco_plan_export_fold(int64_t n, int64_t m, int64_t k, paco_semiring sr, paco_part_mode part,
+                                  int32_t p, int32_t split_k, paco_precision prec, int32_t num_cus,
+                                  paco_plan_info* info, int32_t* pads, int32_t* item_fold, int32_t* fold_list);
 
 #ifdef __cplusplus
 }

@@ -131,7 +131,8 @@ class Timing(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_wg", ctypes.c_int32), ("n_items", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("n_srcs", ctypes.c_int32), ("tile", ctypes.c_int32), ("red_vec", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32), ("temp_elems", ctypes.c_int64)]
+                ("xcd_remap", ctypes.c_int32), ("temp_elems", ctypes.c_int64), ("fused", ctypes.c_int32),
+                ("n_fold_list", ctypes.c_int32)]
 
 
 class PartOpts(ctypes.Structure):
@@ -228,6 +229,9 @@ def lib():
                                  i64, ctypes.POINTER(i64)]
     L.paco_plan_export.argtypes = [i64, i64, i64, ci, ci, ctypes.c_int32, ctypes.c_int32, ci,
                                    ctypes.c_int32, ctypes.POINTER(PlanInfo), vp, vp, vp, vp]
+    L.paco_plan_export_fold.argtypes = [i64, i64, i64, ci, ci, ctypes.c_int32, ctypes.c_int32, ci,
+                                        ctypes.c_int32, ctypes.POINTER(PlanInfo), vp, vp, vp]
+    L.paco_plan_export_fold.restype = ci
     L.paco_server_clock.restype = ctypes.c_double
     L.paco_server_create.argtypes = [vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
     L.paco_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
@@ -343,6 +347,23 @@ def plan_export(n, m, k, semiring, part="paco", p=256, split_k=0, precision="aut
     _check(L.paco_plan_export(*args, ctypes.byref(info), ptr(items), ptr(wg), ptr(tiles), ptr(srcs)))
     d = {f[0]: getattr(info, f[0]) for f in PlanInfo._fields_}
     return (items[:info.n_items], wg, tiles[:info.n_tiles], srcs[:info.n_srcs], d)
+
+
+def plan_export_fold(n, m, k, semiring, part="paco", p=256, split_k=0, precision="auto", num_cus=256):
+    """Host-only: the fused-fold tables of the plan plan_export returns:
+    (pads per tile, item_fold (n_items x 2), fold_list, info)."""
+    import numpy as np
+    L = lib()
+    info = PlanInfo()
+    args = (n, m, k, SEMIRING[semiring], PART[part], p, split_k, PRECISION[precision], num_cus)
+    _check(L.paco_plan_export_fold(*args, ctypes.byref(info), None, None, None))
+    pads = np.zeros(max(info.n_tiles, 1), np.int32)
+    itf = np.zeros((max(info.n_items, 1), 2), np.int32)
+    fl = np.zeros(max(info.n_fold_list, 1), np.int32)
+    ptr = lambda a: ctypes.c_void_p(a.ctypes.data)
+    _check(L.paco_plan_export_fold(*args, ctypes.byref(info), ptr(pads), ptr(itf), ptr(fl)))
+    d = {f[0]: getattr(info, f[0]) for f in PlanInfo._fields_}
+    return pads[:info.n_tiles], itf[:info.n_items], fl[:info.n_fold_list], d
 
 
 def _ptr(t):

@@ -36,6 +36,9 @@ DevPlan::~DevPlan() {
   if (d_wg_off) (void)hipFree(d_wg_off);
   if (d_tiles) (void)hipFree(d_tiles);
   if (d_srcs) (void)hipFree(d_srcs);
+  if (d_item_fold) (void)hipFree(d_item_fold);
+  if (d_fold_list) (void)hipFree(d_fold_list);
+  if (d_fold_cnt) (void)hipFree(d_fold_cnt);
 }
 
 template <class T>
@@ -53,6 +56,14 @@ paco_status upload_plan(paco_ctx ctx, DevPlan* dp) {
   if ((e = upload(&dp->d_wg_off, dp->h.wg_off)) != hipSuccess) return hip_fail(ctx, e, "plan upload");
   if ((e = upload(&dp->d_tiles, dp->h.tiles)) != hipSuccess) return hip_fail(ctx, e, "plan upload");
   if ((e = upload(&dp->d_srcs, dp->h.srcs)) != hipSuccess) return hip_fail(ctx, e, "plan upload");
+  if (dp->h.fused) {
+    if ((e = upload(&dp->d_item_fold, dp->h.item_fold)) != hipSuccess) return hip_fail(ctx, e, "plan upload");
+    if ((e = upload(&dp->d_fold_list, dp->h.fold_list)) != hipSuccess) return hip_fail(ctx, e, "plan upload");
+    // one counter per cell, zero between calls (each call's folding
+    // workgroups reset the counters they complete)
+    if ((e = upload(&dp->d_fold_cnt, std::vector<uint32_t>(dp->h.tiles.size(), 0u))) != hipSuccess)
+      return hip_fail(ctx, e, "plan upload");
+  }
   return PACO_OK;
 }
 
@@ -554,7 +565,16 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
   for (size_t i = 0; i < pcs.size(); ++i) tp[i] = {pcs[i], 0, part != PACO_PART_GRID ? pcs[i].proc : (int)i};
   const int nwg = part != PACO_PART_GRID ? p : (int)pcs.size();
   std::vector<ProbGeom> geom{{n, mu, ku}};
-  np->h = build_plan(tp, nwg, part != PACO_PART_GRID, geom);
+  // the temporary faces are folded by a separate launch: folding inside
+  // the product kernel (the last piece to finish a cell folds it) measured
+  // slower on this device, 22.5 against 16.0 us a call on the (min,+)
+  // 384 x 256 x 320 product, since the device-scope release and acquire
+  // around every counted item and the one-workgroup fold cost more than the
+  // second launch, whose start overlaps the first one's tail.
+  // PACO_FUSE_FOLD=1 fuses, 2 fuses plans whose cells are all small.
+  int fuse = 0;
+  if (const char* ef = getenv("PACO_FUSE_FOLD")) fuse = std::min(2, std::max(0, atoi(ef)));
+  np->h = build_plan(tp, nwg, part != PACO_PART_GRID, geom, 0, 4, fuse);
   np->tile = tile;
   np->fam = fam;
   np->p = p;
@@ -611,6 +631,35 @@ extern "C" paco_status paco_plan_export(int64_t n, int64_t m, int64_t k, paco_se
   info->red_vec = h.red_vec;
   info->xcd_remap = h.xcd_remap ? 1 : 0;
   info->temp_elems = h.temp_elems;
+  info->fused = h.fused ? 1 : 0;
+  info->n_fold_list = (int32_t)h.fold_list.size();
+  return PACO_OK;
+}
+
+extern "C" paco_status paco_plan_export_fold(int64_t n, int64_t m, int64_t k, paco_semiring sr, paco_part_mode part,
+                                             int32_t p, int32_t split_k, paco_precision prec, int32_t num_cus,
+                                             paco_plan_info* info, int32_t* pads, int32_t* item_fold,
+                                             int32_t* fold_list) {
+  paco_plan_info in = info ? *info : paco_plan_info{};
+  paco_status st = paco_plan_export(n, m, k, sr, part, p, split_k, prec, num_cus, &in, nullptr, nullptr, nullptr,
+                                    nullptr);
+  if (st != PACO_OK) return st;
+  const bool fill = pads && item_fold && fold_list;
+  if (fill && info && (info->n_tiles < in.n_tiles || info->n_items < in.n_items ||
+                       info->n_fold_list < in.n_fold_list))
+    return PACO_ERR_INVALID_ARG;
+  if (fill) {
+    int pr = -1;
+    if (sr == PACO_SR_PLUS_TIMES_F32) pr = prec == PACO_PREC_AUTO ? auto_precision(k) : (int)prec;
+    DevPlan dp;
+    make_mm_plan((int)sr, n, m, k, (int)part, p, split_k, pr, num_cus, &dp,
+                 p == 0 ? plan_kcut_cost((int)sr) : default_kcut_cost((int)sr));
+    const HostPlan& h = dp.h;
+    for (size_t i = 0; i < h.tiles.size(); ++i) pads[i] = h.tiles[i].pad;
+    for (size_t i = 0; i < h.item_fold.size(); ++i) item_fold[i] = h.item_fold[i];
+    for (size_t i = 0; i < h.fold_list.size(); ++i) fold_list[i] = h.fold_list[i];
+  }
+  if (info) *info = in;
   return PACO_OK;
 }
 
@@ -705,7 +754,11 @@ void pack_tables(HostTables* t) {
   t->wg_off = al(t->items_off + h.items.size() * sizeof(WorkItem));
   t->tiles_off = al(t->wg_off + h.wg_off.size() * sizeof(int32_t));
   t->srcs_off = al(t->tiles_off + h.tiles.size() * sizeof(RedTile));
-  const uint64_t end = t->srcs_off + h.srcs.size() * sizeof(RedSrc);
+  t->item_fold_off = al(t->srcs_off + h.srcs.size() * sizeof(RedSrc));
+  t->fold_list_off = al(t->item_fold_off + h.item_fold.size() * sizeof(int32_t));
+  // fold counters: zeros, copied with the tables at every call
+  t->fold_cnt_off = al(t->fold_list_off + h.fold_list.size() * sizeof(int32_t));
+  const uint64_t end = t->fold_cnt_off + (h.fused ? h.tiles.size() * sizeof(uint32_t) : 0);
   t->faces_off = al(end);
   t->blob.assign(end, 0);
   auto put = [&](uint64_t off, const void* src, size_t bytes) {
@@ -715,6 +768,8 @@ void pack_tables(HostTables* t) {
   put(t->wg_off, h.wg_off.data(), h.wg_off.size() * sizeof(int32_t));
   put(t->tiles_off, h.tiles.data(), h.tiles.size() * sizeof(RedTile));
   put(t->srcs_off, h.srcs.data(), h.srcs.size() * sizeof(RedSrc));
+  put(t->item_fold_off, h.item_fold.data(), h.item_fold.size() * sizeof(int32_t));
+  put(t->fold_list_off, h.fold_list.data(), h.fold_list.size() * sizeof(int32_t));
 }
 
 }  // namespace paco
@@ -807,9 +862,10 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
   const double kc = kc_in > 0 ? kc_in : plan_kcut_cost((int)d->sr);
   const char* tenv = getenv(is_bool ? "PACO_BOOL_TILE" : (d->sr == PACO_SR_PLUS_TIMES_F32 ? "PACO_RING_TILE"
                                                                                            : "PACO_INT_TILE"));
-  snprintf(key, sizeof key, "mm/%d/%lld/%lld/%lld/%d/%d/%d/%d/%g/%.8s/%llx/%d", (int)d->sr, (long long)z.n,
+  const char* fenv = getenv("PACO_FUSE_FOLD");
+  snprintf(key, sizeof key, "mm/%d/%lld/%lld/%lld/%d/%d/%d/%d/%g/%.8s/%.2s/%llx/%d", (int)d->sr, (long long)z.n,
            (long long)z.m, (long long)z.k, part, p, d->grid_split_k, z.prec, kc, tenv ? tenv : "",
-           (unsigned long long)whash, force_tile);
+           fenv ? fenv : "", (unsigned long long)whash, force_tile);
   DevPlan* dp = nullptr;
   // device tables of the plan and the temporary faces: the plan's own
   // allocations and the context's workspace, or (fx) the caller's fixed
@@ -818,6 +874,9 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
   const int32_t* d_wg_off = nullptr;
   const RedTile* d_tiles = nullptr;
   const RedSrc* d_srcs = nullptr;
+  const int32_t* d_item_fold = nullptr;
+  const int32_t* d_fold_list = nullptr;
+  uint32_t* d_fold_cnt = nullptr;
   void* ws = nullptr;
   paco_status st = PACO_OK;
   if (!fx) {
@@ -841,6 +900,9 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
     d_wg_off = dp->d_wg_off;
     d_tiles = dp->d_tiles;
     d_srcs = dp->d_srcs;
+    d_item_fold = dp->d_item_fold;
+    d_fold_list = dp->d_fold_list;
+    d_fold_cnt = dp->d_fold_cnt;
     ws = ctx->ws;
   } else {
     auto itp = ctx->host_plans.find(key);
@@ -880,6 +942,11 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
     d_wg_off = (const int32_t*)(base + ht->wg_off);
     d_tiles = (const RedTile*)(base + ht->tiles_off);
     d_srcs = (const RedSrc*)(base + ht->srcs_off);
+    if (dp->h.fused) {
+      d_item_fold = (const int32_t*)(base + ht->item_fold_off);
+      d_fold_list = (const int32_t*)(base + ht->fold_list_off);
+      d_fold_cnt = (uint32_t*)(base + ht->fold_cnt_off);
+    }
     ws = base + ht->faces_off;
   }
 
@@ -893,6 +960,15 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
   pr.vec_ok = ring_vec_ok(d->A, z.lda, d->B, z.ldb, z.m, z.k) ? 1 : 0;
   pr.stamps = ctx->stamps;
   pr.stamp_cap = ctx->stamps ? ctx->stamp_cap : 0;
+  const int rvec = (dp->h.red_vec == 4 && (uintptr_t)d->C % 16 == 0 && z.ldc % 4 == 0) ? 4 : 1;
+  if (dp->h.fused) {
+    pr.item_fold = d_item_fold;
+    pr.fold_list = d_fold_list;
+    pr.fold_tiles = d_tiles;
+    pr.fold_srcs = d_srcs;
+    pr.fold_cnt = d_fold_cnt;
+    pr.fold_vec = rvec;
+  }
   {
   TimeScope ts(ctx, 0);
   if (dp->fam == 0)
@@ -904,9 +980,8 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
     e = launch_ring(z.prec, dp->tile, pr, d_items, d_wg_off, dp->h.nwg, dp->h.xcd_remap, ws, ctx->stream);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "semiring kernel launch");
-  if (!dp->h.tiles.empty()) {
+  if (!dp->h.tiles.empty() && !dp->h.fused) {
     TimeScope ts(ctx, 1);
-    const int rvec = (dp->h.red_vec == 4 && (uintptr_t)d->C % 16 == 0 && z.ldc % 4 == 0) ? 4 : 1;
     e = launch_reduce(is_bool ? SR_BOOL : (int)d->sr, pr, d_tiles, (int)dp->h.tiles.size(), d_srcs, ws,
                       ctx->stream, rvec);
     if (e != hipSuccess) return hip_fail(ctx, e, "reduce launch");

@@ -24,6 +24,9 @@ struct DevPlan {
   int32_t* d_wg_off = nullptr;
   RedTile* d_tiles = nullptr;
   RedSrc* d_srcs = nullptr;
+  int32_t* d_item_fold = nullptr;   // fused folding (HostPlan::fused)
+  int32_t* d_fold_list = nullptr;
+  uint32_t* d_fold_cnt = nullptr;
   virtual ~DevPlan();
 };
 
@@ -34,6 +37,7 @@ struct HostTables {
   DevPlan plan;   // device pointers stay null
   std::vector<unsigned char> blob;
   uint64_t items_off = 0, wg_off = 0, tiles_off = 0, srcs_off = 0, faces_off = 0;
+  uint64_t item_fold_off = 0, fold_list_off = 0, fold_cnt_off = 0;
 };
 
 // Caller-provided device memory for a call that allocates nothing.

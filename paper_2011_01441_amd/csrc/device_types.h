@@ -43,6 +43,18 @@ struct ProbRef {
   uint64_t* stamps;    // null, or 4 words per processor: start and end of
                        // its work on the device's 100 MHz clock, its XCC_ID
                        // and HW_ID hardware registers
+  // Fused folding of temporary faces (null item_fold: a separate launch
+  // folds them): item i covers the reduction cells fold_list[item_fold[2i]
+  // .. + item_fold[2i+1]); cell c is fold_tiles[c] (its pad holds the
+  // number of pieces covering it) with sources in fold_srcs; fold_cnt
+  // holds one counter per cell, zero between calls.
+  const int32_t* item_fold;
+  const int32_t* fold_list;
+  const struct RedTile* fold_tiles;
+  const struct RedSrc* fold_srcs;
+  uint32_t* fold_cnt;
+  int32_t fold_vec;    // 4: cells and faces allow 128-bit access
+  int32_t fold_pad;
 };
 
 // A sub-cuboid [n0,n1) x [m0,m1) x [k0,k1) of problem `prob`.  out_off < 0:

@@ -11,6 +11,7 @@
 // step through double-buffered LDS.
 #include "kcommon.h"
 #include "kernels.h"
+#include "kfold.h"
 
 namespace paco {
 namespace {
@@ -149,6 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_semiring_bool(ProbRef pr, const Wo
         }
       }
     }
+    fold_after_item<ROr, kThreads>(pr, it, ws);
   }
   stamp_end(pr, q);
 }

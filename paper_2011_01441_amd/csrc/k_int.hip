@@ -18,6 +18,7 @@
 // thresholding the final value at -2^29 reproduces the absorbing NEG_INF.
 #include "kcommon.h"
 #include "kernels.h"
+#include "kfold.h"
 
 namespace paco {
 namespace {
@@ -28,6 +29,7 @@ constexpr int kLChunk = 8;
 
 struct OpMin {
   using T = uint32_t;
+  using Red = RMin;   // the fold of temporary faces
   static __device__ __forceinline__ T acc0() { return (T)kMinPlusInf; }
   static __device__ __forceinline__ T pad() { return (T)kMinPlusInf; }
   // pad_with(v, pad()) is the padding value, pad_with(v, nopad()) is v
@@ -40,6 +42,7 @@ struct OpMin {
 
 struct OpMax {
   using T = int32_t;
+  using Red = RMax;
   static __device__ __forceinline__ T acc0() { return (T)0x80000000u; }
   static __device__ __forceinline__ T pad() { return kMaxPlusNegInf; }
   static __device__ __forceinline__ T nopad() { return 0x7fffffff; }
@@ -169,6 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_semiring_int(ProbRef pr, const Wor
         }
       }
     }
+    fold_after_item<typename Op::Red, kThreads>(pr, it, (const typename Op::Red::T*)ws);
   }
   stamp_end(pr, q);
 }

@@ -27,6 +27,7 @@
 
 #include "kcommon.h"
 #include "kernels.h"
+#include "kfold.h"
 
 namespace paco {
 namespace {
@@ -381,6 +382,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_ring(ProbRef pr, const WorkIte
         else epilogue(std::false_type{});
       }
     }
+    fold_after_item<RSum, kThreads>(pr, it, ws);
   }
   stamp_end(pr, q);
 }

@@ -16,7 +16,7 @@
 namespace paco {
 
 HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_remap,
-                    const std::vector<ProbGeom>& geom, int64_t temp_base, int red_vec) {
+                    const std::vector<ProbGeom>& geom, int64_t temp_base, int red_vec, int fuse) {
   HostPlan hp;
   hp.nwg = nwg;
   hp.xcd_remap = xcd_remap && nwg % 8 == 0;
@@ -45,10 +45,12 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
   }
   hp.temp_elems = cur - temp_base;
 
+  std::vector<int> item_piece;   // piece of each item
   hp.wg_off.assign(nwg + 1, 0);
   for (int w = 0; w < nwg; ++w) {
     hp.wg_off[w] = (int32_t)hp.items.size();
     for (int i : by_wg[w]) {
+      item_piece.push_back(i);
       const Piece& p = pieces[i].pc;
       WorkItem it;
       it.prob = pieces[i].prob;
@@ -74,6 +76,36 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
   std::map<int, std::vector<int>> temps_of;  // prob -> temp piece indices
   for (size_t i = 0; i < pieces.size(); ++i)
     if (off[i] >= 0) temps_of[pieces[i].prob].push_back((int)i);
+  if (fuse == 2) {   // fused unless some cell's fold is large
+    fuse = 1;
+    for (auto& kv : temps_of) {
+      std::vector<int64_t> rb, cb;
+      for (int i : kv.second) {
+        rb.push_back(pieces[i].pc.n0); rb.push_back(pieces[i].pc.n1);
+        cb.push_back(pieces[i].pc.m0); cb.push_back(pieces[i].pc.m1);
+      }
+      std::sort(rb.begin(), rb.end()); rb.erase(std::unique(rb.begin(), rb.end()), rb.end());
+      std::sort(cb.begin(), cb.end()); cb.erase(std::unique(cb.begin(), cb.end()), cb.end());
+      const size_t Cn = cb.size() - 1;
+      std::vector<int64_t> nsrc((rb.size() - 1) * Cn, 0);
+      for (int i : kv.second) {
+        const Piece& p = pieces[i].pc;
+        size_t r0 = std::lower_bound(rb.begin(), rb.end(), p.n0) - rb.begin();
+        size_t r1 = std::lower_bound(rb.begin(), rb.end(), p.n1) - rb.begin();
+        size_t c0 = std::lower_bound(cb.begin(), cb.end(), p.m0) - cb.begin();
+        size_t c1 = std::lower_bound(cb.begin(), cb.end(), p.m1) - cb.begin();
+        for (size_t r = r0; r < r1; ++r)
+          for (size_t c = c0; c < c1; ++c) nsrc[r * Cn + c] += 1;
+      }
+      for (size_t r = 0; r + 1 < rb.size(); ++r)
+        for (size_t c = 0; c < Cn; ++c)
+          if (nsrc[r * Cn + c] > 0 &&
+              (rb[r + 1] - rb[r]) * (cb[c + 1] - cb[c]) * (nsrc[r * Cn + c] + 1) * 4 > kFuseCellBytes)
+            fuse = 0;
+    }
+  }
+  hp.fused = fuse == 1;
+  std::vector<std::vector<int32_t>> piece_cells(hp.fused ? pieces.size() : 0);
   for (auto& kv : temps_of) {
     const int prob = kv.first;
     const std::vector<int>& tp = kv.second;
@@ -113,9 +145,29 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
           hp.srcs.push_back(s);
         }
         int32_t s1 = (int32_t)hp.srcs.size();
+        int64_t i0 = rb[r], i1 = rb[r + 1], j0 = cb[c], j1 = cb[c + 1];
+        if (hp.fused) {
+          // one tile per cell; every piece of the problem meeting the cell
+          // (its faces' pieces and the lowest-k ones writing C) counts
+          const int32_t cell = (int32_t)hp.tiles.size();
+          RedTile t;
+          t.prob = prob;
+          t.i0 = (int32_t)i0; t.i1 = (int32_t)i1;
+          t.j0 = (int32_t)j0; t.j1 = (int32_t)j1;
+          t.s0 = s0; t.s1 = s1; t.pad = 0;
+          for (size_t i = 0; i < pieces.size(); ++i) {
+            const Piece& p = pieces[i].pc;
+            if (pieces[i].prob != prob || p.empty()) continue;
+            if (p.n0 < i1 && p.n1 > i0 && p.m0 < j1 && p.m1 > j0) {
+              piece_cells[i].push_back(cell);
+              t.pad += 1;
+            }
+          }
+          hp.tiles.push_back(t);
+          continue;
+        }
         // split the cell into tiles of at most 256*vec columns and about
         // 1024 elements (many workgroups: the fold is bandwidth-bound)
-        int64_t i0 = rb[r], i1 = rb[r + 1], j0 = cb[c], j1 = cb[c + 1];
         int64_t cw = std::min<int64_t>(j1 - j0, 256 * vec);
         int64_t rh = std::max<int64_t>(1, (256 * vec) / cw);
         for (int64_t ii = i0; ii < i1; ii += rh)
@@ -129,6 +181,15 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
           }
       }
     (void)geom;
+  }
+  if (hp.fused) {
+    hp.item_fold.assign(2 * hp.items.size(), 0);
+    for (size_t it = 0; it < hp.items.size(); ++it) {
+      const std::vector<int32_t>& cl = piece_cells[item_piece[it]];
+      hp.item_fold[2 * it] = (int32_t)hp.fold_list.size();
+      hp.item_fold[2 * it + 1] = (int32_t)cl.size();
+      hp.fold_list.insert(hp.fold_list.end(), cl.begin(), cl.end());
+    }
   }
   return hp;
 }

@@ -24,6 +24,12 @@ struct HostPlan {
   std::vector<RedSrc> srcs;
   int64_t temp_elems = 0;          // workspace elements for temporary faces
   int red_vec = 1;                 // reduction vector width (4 when aligned)
+  // fused folding (the product kernel folds the cells; `tiles` are whole
+  // cells, each tile's pad the number of pieces covering it): per item
+  // (begin, count) into fold_list, the cells the item covers
+  bool fused = false;
+  std::vector<int32_t> item_fold;
+  std::vector<int32_t> fold_list;
   // statistics over non-empty pieces
   int32_t n_pieces = 0, n_kcuts = 0;
   int64_t vmax = 0, vmin = 0;
@@ -43,7 +49,13 @@ struct TaggedPiece {
 // `red_vec` 4 asks for 4-wide reduction tiles; the plan falls back to 1
 // unless every face offset, width and column origin is a multiple of 4
 // (the caller checks the alignment of C itself).
+// fuse: 0 a separate fold launch (cells cut into tiles of about 1024
+// elements); 1 fused folding; 2 fused when no cell's fold reads more than
+// kFuseCellBytes (one workgroup folds each cell).  The library's calls use
+// 0 unless PACO_FUSE_FOLD says otherwise.
+constexpr int64_t kFuseCellBytes = 256 << 10;
 HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_remap,
-                    const std::vector<ProbGeom>& geom, int64_t temp_base = 0, int red_vec = 4);
+                    const std::vector<ProbGeom>& geom, int64_t temp_base = 0, int red_vec = 4,
+                    int fuse = 0);
 
 }  // namespace paco

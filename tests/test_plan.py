@@ -197,3 +197,79 @@ def test_multi_piece_ring_plan_replay():
     A, B = workloads.small_int_operands(300, 200, 700, seed=4)
     C, _ = replay("ring", A.astype(np.int64), B.astype(np.int64), 300, 200, 700, part="multi", p=97)
     np.testing.assert_array_equal(C, A.astype(np.int64) @ B.astype(np.int64))
+
+
+def replay_fused(sr, A, B, n, m, k, seed, **kw):
+    """The fused-fold plan replayed with the pieces finishing in a random
+    order: each finished item counts itself in every cell it covers; the
+    item completing a cell's count folds it (C then its faces, in list
+    order) and resets the counter."""
+    items, wg, tiles, srcs, info = P.plan_export(n, m, k, sr, **kw)
+    pads, itf, fl, info2 = P.plan_export_fold(n, m, k, sr, **kw)
+    assert info["fused"] == 1 and info2["n_fold_list"] == len(fl)
+    # each cell's count is the number of items whose rectangle meets it,
+    # and each item lists exactly the cells its rectangle meets
+    for idx, it in enumerate(items):
+        _, n0, n1, m0, m1, k0, k1, off = it
+        meet = [c for c, t in enumerate(tiles) if t[1] < n1 and t[2] > n0 and t[3] < m1 and t[4] > m0]
+        b, cnt = itf[idx]
+        assert sorted(fl[b:b + cnt].tolist()) == meet
+    for c in range(len(tiles)):
+        assert pads[c] == sum(c in fl[b:b + cnt].tolist() for b, cnt in itf)
+    C = np.full((n, m), 12345678, np.int64)
+    ws = np.full(max(info["temp_elems"], 1), -7777, np.int64)
+    counter = np.zeros(len(tiles), np.int64)
+    folded = np.zeros(len(tiles), np.int64)
+    order = np.random.default_rng(seed).permutation(len(items))
+    for idx in order:
+        it = items[idx]
+        _, n0, n1, m0, m1, k0, k1, off = it
+        part = _partial(sr, A, B, it)
+        if off < 0:
+            C[n0:n1, m0:m1] = part
+        else:
+            ws[off:off + part.size] = part.reshape(-1)
+        b, cnt = itf[idx]
+        for c in fl[b:b + cnt]:
+            counter[c] += 1
+            if counter[c] == pads[c]:
+                counter[c] = 0
+                folded[c] += 1
+                _, i0, i1, j0, j1, s0, s1 = tiles[c]
+                for s in range(s0, s1):
+                    o, ld, r0, c0 = srcs[s]
+                    rr = np.arange(i0, i1)[:, None] - r0
+                    cc = np.arange(j0, j1)[None, :] - c0
+                    C[i0:i1, j0:j1] = _fold(sr, C[i0:i1, j0:j1], ws[o + rr * ld + cc])
+    assert (folded == 1).all() and (counter == 0).all()
+    return C
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("sr,n,m,k,p", [("minplus", 384, 256, 320, 0), ("minplus", 97, 130, 75, 0),
+                                        ("maxplus", 257, 65, 900, 64), ("minplus", 70, 50, 3000, 37)])
+def test_fused_fold_plan_replay(sr, n, m, k, p, seed, monkeypatch):
+    """Plans whose cells are small fold inside the product kernel: whatever
+    order the pieces finish in, every cell is folded exactly once, by the
+    last piece to reach it, after every piece covering it has written, and
+    the counters end at zero.  (PACO_FUSE_FOLD=1 fuses plans whose cells
+    are larger too.)"""
+    monkeypatch.setenv("PACO_FUSE_FOLD", "1")
+    gen = workloads.minplus_operands if sr == "minplus" else workloads.maxplus_operands
+    A, B = gen(n, m, k, seed=seed + 11)
+    C = replay_fused(sr, A, B, n, m, k, seed, p=p)
+    np.testing.assert_array_equal(C, (oracle.minplus if sr == "minplus" else oracle.maxplus)(A, B))
+
+
+def test_fold_policy(monkeypatch):
+    # default: a separate fold launch
+    _, _, _, _, info = P.plan_export(384, 256, 320, "minplus", p=0)
+    assert info["fused"] == 0
+    # PACO_FUSE_FOLD=2 fuses plans whose cells are small: not the long-k
+    # ring product, where every cell is a 256 x 256 tile with seven faces
+    # (1.75 MiB read by one fold)
+    monkeypatch.setenv("PACO_FUSE_FOLD", "2")
+    _, _, _, _, info = P.plan_export(2048, 1024, 65536, "ring", p=256, precision="bf16x3")
+    assert info["fused"] == 0
+    _, _, _, _, info = P.plan_export(384, 256, 320, "minplus", p=0)
+    assert info["fused"] == 1
