@@ -493,7 +493,7 @@ def config_summary(torch, P, ctx, label, name, steps):
     else:
         tile_env = {"bool": "PACO_BOOL_TILE"}.get(w["kind"], "PACO_INT_TILE")
         best = None
-        for tile in (0, 1, 2, 3):
+        for tile in ((0, 1, 2, 3) if w["kind"] == "bool" else (0, 1, 2, 3, 4)):
             os.environ[tile_env] = str(tile)
             for sk in (1, 2, 4, 8, 16, 32, 64):
                 f = (lambda sk=sk: call(ctx, w, Ad, Bd, C, part="grid", split_k=sk))
@@ -715,7 +715,8 @@ def main():
         log(f"grid: {gms:.3f} ms/step")
     elif not args.no_grid and w["kind"] != "strassen":
         tile_env = {"ring": "PACO_RING_TILE", "bool": "PACO_BOOL_TILE"}.get(w["kind"], "PACO_INT_TILE")
-        tiles = {"ring": (4, 0, 1, 2) if prec != "bf16x6" else (0, 1, 2)}.get(w["kind"], (0, 1, 2, 3))
+        tiles = {"ring": (4, 0, 1, 2) if prec != "bf16x6" else (0, 1, 2),
+                 "bool": (0, 1, 2, 3)}.get(w["kind"], (0, 1, 2, 3, 4))
         best = None
         for tile in tiles:
             os.environ[tile_env] = str(tile)

@@ -95,11 +95,11 @@ paco_status ensure_ws(paco_ctx ctx, uint64_t bytes) {
 int choose_int_tile(const std::vector<Piece>& pcs) {
   // critical-path padded work of each tile shape, small tiles weighted by
   // their lower efficiency
-  const int cand[4] = {INT_T128x128, INT_T256x64, INT_T64x128, INT_T64x64};
-  const double eff[4] = {1.0, 1.0, 1.15, 1.35};
+  const int cand[5] = {INT_T128x128, INT_T256x64, INT_T64x128, INT_T64x64, INT_T128x64};
+  const double eff[5] = {1.0, 1.0, 1.15, 1.35, 1.1};
   int best = INT_T128x128;
   double bestc = 1e300;
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < 5; ++c) {
     IntTileShape ts = int_tile_shape(cand[c]);
     double worst = 0;
     for (const Piece& p : pcs) {
@@ -465,20 +465,21 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
       // These kernels stream about 8 elements per byte, so a k-cut also
       // costs L2 reuse (concurrent pieces no longer walk k in step); the
       // overhead term and the face traffic stand for that.
-      const int ci[4] = {INT_T128x128, INT_T256x64, INT_T64x128, INT_T64x64};
-      const double ei[4] = {1.0, 1.14, 1.05, 0.95};
+      const int ci[5] = {INT_T128x128, INT_T256x64, INT_T64x128, INT_T64x64, INT_T128x64};
+      const double ei[5] = {1.0, 1.14, 1.05, 0.95, 1.0};
       const int cb[4] = {BOOL_T512x32W, BOOL_T128x128W, BOOL_T256x64W, BOOL_T64x64W};
       const double eb[4] = {1.0, 1.0, 0.98, 1.08};
+      const int ncand = fam == 0 ? 5 : 4;
       const double rate_cu = fam == 0 ? 70e9 : 110e9;      // elements (words) per second per CU
       const double k_ovh = fam == 0 ? 64.0 : 128.0;        // prologue + epilogue, in k units
       const double kcs[4] = {1.0, 4.0, 16.0, 64.0};
       const int nkc = kcut_cost > 0 ? 1 : 4;
-      const int forced = force_tile >= 0 ? force_tile : env_tile(tile_env, 4, -1);
+      const int forced = force_tile >= 0 ? force_tile : env_tile(tile_env, ncand, -1);
       const double work = (double)n * (double)mu * (double)k;
       double bestc = 1e300;
       for (int ik = 0; ik < nkc; ++ik) {
         po.kcut_cost = kcut_cost > 0 ? kcut_cost : kcs[ik];
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < ncand; ++c) {
           const int t = fam == 0 ? ci[c] : cb[c];
           if (forced >= 0 && t != forced) continue;
           int tm_, tn_;
@@ -531,13 +532,13 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
       if (fam == 0) tile = choose_int_tile(pcs);
       else if (fam == 1) tile = choose_bool_tile(pcs);
       else tile = choose_ring_tile(pcs, prec);
-      tile = env_tile(tile_env, fam == 2 ? 5 : 4, tile);
+      tile = env_tile(tile_env, fam == 2 ? 5 : (fam == 0 ? kIntTiles : 4), tile);
       if (force_tile >= 0) tile = force_tile;
     }
   } else {
     if (fam == 0) {
       tile = m <= 64 ? INT_T256x64 : (n <= 64 ? INT_T64x128 : INT_T128x128);
-      tile = env_tile("PACO_INT_TILE", 4, tile);
+      tile = env_tile("PACO_INT_TILE", kIntTiles, tile);
       IntTileShape ts = int_tile_shape(tile);
       tm = ts.tm; tn = ts.tn;
     } else if (fam == 1) {

@@ -195,6 +195,9 @@ hipError_t launch_op(int tile, const ProbRef& pr, const WorkItem* items, const i
     case INT_T64x128:
       hipLaunchKernelGGL((k_semiring_int<Op, 64, 128, 4, 8>), g, b, 0, s, pr, items, wg_off, nwg, xcd, (T*)ws);
       break;
+    case INT_T128x64:
+      hipLaunchKernelGGL((k_semiring_int<Op, 128, 64, 8, 4>), g, b, 0, s, pr, items, wg_off, nwg, xcd, (T*)ws);
+      break;
     default:
       return hipErrorInvalidValue;
   }
@@ -218,6 +221,9 @@ int occupancy_op(int tile) {
     case INT_T64x128:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 64, 128, 4, 8>, kThreads, 0);
       break;
+    case INT_T128x64:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 128, 64, 8, 4>, kThreads, 0);
+      break;
   }
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }
@@ -234,6 +240,7 @@ IntTileShape int_tile_shape(int tile) {
     case INT_T256x64: return {256, 64};
     case INT_T64x64: return {64, 64};
     case INT_T64x128: return {64, 128};
+    case INT_T128x64: return {128, 64};
   }
   return {0, 0};
 }

@@ -8,7 +8,8 @@ namespace paco {
 
 // Tile shapes of the integer (VALU) semiring kernel: output tile TM x TN,
 // k-step 32, 256 threads.
-enum IntTile : int { INT_T128x128 = 0, INT_T256x64 = 1, INT_T64x64 = 2, INT_T64x128 = 3 };
+enum IntTile : int { INT_T128x128 = 0, INT_T256x64 = 1, INT_T64x64 = 2, INT_T64x128 = 3, INT_T128x64 = 4 };
+constexpr int kIntTiles = 5;
 struct IntTileShape { int tm, tn; };
 IntTileShape int_tile_shape(int tile);
 // Workgroups of the kernel that fit on one compute unit at once (1 when the

@@ -95,7 +95,7 @@ extern "C" paco_status paco_tune(paco_ctx ctx, const paco_mm_desc* d, paco_tune_
         }
   } else {
     const bool is_bool = d->sr == PACO_SR_OR_AND_B1;
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < (is_bool ? 4 : kIntTiles); ++t) {
       int occ = is_bool ? bool_occupancy(t) : int_occupancy((int)d->sr, t);
       occ = std::min(std::max(occ, 1), 8);
       for (int f : {1, 4})

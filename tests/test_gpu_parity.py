@@ -232,3 +232,17 @@ def test_weighted_split_exact(ctx):
         assert res["p"] == 256 and res["max_piece_volume"] > 2 * res["min_piece_volume"]
     finally:
         ctx.set_processor_weights(None)
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("sr,n,m,k", [("minplus", 300, 77, 129), ("maxplus", 517, 64, 700), ("minplus", 129, 260, 96)])
+def test_int_tiles_bit_exact(ctx, tile, sr, n, m, k, monkeypatch):
+    """Every (min,+)/(max,+) tile shape (forced through PACO_INT_TILE),
+    ragged sizes, k-cuts from the default plan: bit-exact."""
+    monkeypatch.setenv("PACO_INT_TILE", str(tile))
+    print(f"case: int tile {tile} {sr} {n}x{m}x{k}", flush=True)
+    gen = workloads.minplus_operands if sr == "minplus" else workloads.maxplus_operands
+    A, B = gen(n, m, k, seed=tile + n)
+    ref = (oracle.minplus if sr == "minplus" else oracle.maxplus)(A, B)
+    for part in ("paco", "grid"):
+        assert np.array_equal(host(ctx.semiring_mm(dev(A), dev(B), sr, part=part)), ref), part
