@@ -377,16 +377,25 @@ static int env_tile(const char* name, int count, int dflt) {
 // epilogue of two steps per tile) wins.  force_tile >= 0 tries that one only.
 std::vector<Piece> ring_partition(int64_t n, int64_t m, int64_t k, int p, int prec, double kcut_cost,
                                   const double* weights, int force_tile, int* tile_out) {
-  const int cand[4] = {RING_T256x256, RING_T256x128, RING_T128x128, RING_T128x64};
-  const double eff[4] = {1.0, 1.1, 1.25, 1.6};
+  // tile shapes tried and their measured relative cost per padded element;
+  // a forced tile (any of the kernel's shapes) is the only candidate
+  const int dcand[4] = {RING_T256x256, RING_T256x128, RING_T128x128, RING_T128x64};
+  const double deff[4] = {1.0, 1.1, 1.25, 1.6};
+  const int fcand[1] = {force_tile};
+  const double feff[1] = {1.0};
+  // (three bf16 parts of a 256 x 256 tile do not fit the LDS: that forced
+  // tile is ignored like an out-of-range one)
+  const bool forced = force_tile >= 0 && force_tile < 5 && !(force_tile == RING_T256x256 && prec == PREC_BF16X6);
+  const int* cand = forced ? fcand : dcand;
+  const double* eff = forced ? feff : deff;
+  const int ncand = forced ? 1 : 4;
   const double k_ovh = 64.0;
   std::vector<Piece> best;
   double bestc = 1e300;
   int bt = -1;
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < ncand; ++c) {
     const int t = cand[c];
-    if (force_tile >= 0 && t != force_tile) continue;
-    if (t == RING_T256x256 && prec == PREC_BF16X6 && force_tile < 0) continue;   // three parts do not fit
+    if (t == RING_T256x256 && prec == PREC_BF16X6 && !forced) continue;   // three parts do not fit
     const RingTileShape ts = ring_tile_shape(t, prec);
     PartOpts po;
     po.p = p;

@@ -246,3 +246,17 @@ def test_int_tiles_bit_exact(ctx, tile, sr, n, m, k, monkeypatch):
     ref = (oracle.minplus if sr == "minplus" else oracle.maxplus)(A, B)
     for part in ("paco", "grid"):
         assert np.array_equal(host(ctx.semiring_mm(dev(A), dev(B), sr, part=part)), ref), part
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+def test_ring_forced_tiles_exact(ctx, tile, prec, monkeypatch):
+    """Every ring tile shape forced through PACO_RING_TILE (the four-wave
+    128 x 128 one included), small integers: exact; the 256 x 256 tile
+    with three bf16 parts falls back to a tile that fits."""
+    monkeypatch.setenv("PACO_RING_TILE", str(tile))
+    n, m, k = 300, 260, 2000
+    print(f"case: ring forced tile {tile} {prec}", flush=True)
+    A, B = workloads.small_int_operands(n, m, k, seed=tile + 3)
+    C = host(ctx.semiring_mm(dev(A), dev(B), "ring", precision=prec, p=64))
+    assert np.array_equal(C.astype(np.float64), oracle.ring_f64(A, B))

@@ -273,3 +273,20 @@ def test_fold_policy(monkeypatch):
     assert info["fused"] == 0
     _, _, _, _, info = P.plan_export(384, 256, 320, "minplus", p=0)
     assert info["fused"] == 1
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x6"])
+def test_forced_ring_tile_plan(tile, prec, monkeypatch):
+    """PACO_RING_TILE forces any of the ring kernel's tile shapes (also the
+    four-wave 128 x 128 one outside the default candidates); the 256 x 256
+    tile cannot hold three bf16 parts and is then ignored.  The plan still
+    covers every (i, j, l) once."""
+    monkeypatch.setenv("PACO_RING_TILE", str(tile))
+    n, m, k = 300, 260, 2000
+    _, _, _, _, info = P.plan_export(n, m, k, "ring", p=64, precision=prec)
+    assert info["tile"] == (tile if not (tile == 4 and prec == "bf16x6") else info["tile"])
+    assert info["tile"] != 4 or prec != "bf16x6"
+    A, B = workloads.small_int_operands(n, m, k, seed=tile)
+    C, _ = replay("ring", A.astype(np.int64), B.astype(np.int64), n, m, k, p=64, precision=prec)
+    np.testing.assert_array_equal(C, oracle.ring_i64(A.astype(np.int64), B.astype(np.int64)))
