@@ -376,26 +376,32 @@ static int env_tile(const char* name, int count, int dflt) {
 // work (weighted by the tile's measured relative cost, plus a prologue and
 // epilogue of two steps per tile) wins.  force_tile >= 0 tries that one only.
 std::vector<Piece> ring_partition(int64_t n, int64_t m, int64_t k, int p, int prec, double kcut_cost,
-                                  const double* weights, int force_tile, int* tile_out) {
+                                  const double* weights, int force_tile, int* tile_out, double min_gain_s) {
   // tile shapes tried and their measured relative cost per padded element;
   // a forced tile (any of the kernel's shapes) is the only candidate
-  const int dcand[4] = {RING_T256x256, RING_T256x128, RING_T128x128, RING_T128x64};
-  const double deff[4] = {1.0, 1.1, 1.25, 1.6};
-  const int fcand[1] = {force_tile};
-  const double feff[1] = {1.0};
   // (three bf16 parts of a 256 x 256 tile do not fit the LDS: that forced
   // tile is ignored like an out-of-range one)
+  const int dcand[4] = {RING_T256x256, RING_T256x128, RING_T128x128, RING_T128x64};
+  const double deff[4] = {1.0, 1.1, 1.25, 1.6};
   const bool forced = force_tile >= 0 && force_tile < 5 && !(force_tile == RING_T256x256 && prec == PREC_BF16X6);
-  const int* cand = forced ? fcand : dcand;
-  const double* eff = forced ? feff : deff;
-  const int ncand = forced ? 1 : 4;
   const double k_ovh = 64.0;
-  std::vector<Piece> best;
-  double bestc = 1e300;
-  int bt = -1;
-  for (int c = 0; c < ncand; ++c) {
-    const int t = cand[c];
-    if (t == RING_T256x256 && prec == PREC_BF16X6 && !forced) continue;   // three parts do not fit
+  double wsum = 0;
+  for (int i = 0; i < p; ++i) wsum += weights ? weights[i] : 1.0;
+  struct Cand {
+    int tile;
+    double eff, lb;
+  };
+  std::vector<Cand> cands;
+  for (int c = 0; c < (forced ? 1 : 4); ++c) {
+    const int t = forced ? force_tile : dcand[c];
+    if (!forced && t == RING_T256x256 && prec == PREC_BF16X6) continue;
+    const RingTileShape ts = ring_tile_shape(t, prec);
+    // no partition does better than the whole padded product spread evenly
+    const double lb = (double)((n + ts.tm - 1) / ts.tm * ts.tm) * (double)((m + ts.tn - 1) / ts.tn * ts.tn) *
+                      ((double)((k + ts.bk - 1) / ts.bk * ts.bk) + k_ovh) / wsum * (forced ? 1.0 : deff[c]);
+    cands.push_back({t, forced ? 1.0 : deff[c], lb});
+  }
+  auto options = [&](int t, bool search) {
     const RingTileShape ts = ring_tile_shape(t, prec);
     PartOpts po;
     po.p = p;
@@ -404,23 +410,60 @@ std::vector<Piece> ring_partition(int64_t n, int64_t m, int64_t k, int p, int pr
     po.q[0] = n >= 2 * ts.tm ? ts.tm : 16;
     po.q[1] = m >= 2 * ts.tn ? ts.tn : 16;
     po.q[2] = ts.bk;
-    po.tile_balance = true;
+    po.tile_balance = search;
     po.tile_n = ts.tm;
     po.tile_m = ts.tn;
     po.tile_k_ovh = k_ovh;
-    std::vector<Piece> v = partition_mm1(n, m, k, po);
+    return po;
+  };
+  auto cost = [&](const std::vector<Piece>& v, const Cand& c) {
+    const RingTileShape ts = ring_tile_shape(c.tile, prec);
     double worst = 0;
     for (const Piece& pc : v) {
       if (pc.empty()) continue;
       const double tiles = (double)((pc.n1 - pc.n0 + ts.tm - 1) / ts.tm) * (double)((pc.m1 - pc.m0 + ts.tn - 1) / ts.tn);
       const double kk = (double)((pc.k1 - pc.k0 + ts.bk - 1) / ts.bk * ts.bk);
       const double w = weights ? weights[pc.proc] : 1.0;
-      worst = std::max(worst, tiles * ts.tm * ts.tn * (kk + k_ovh) * eff[c] / w);
+      worst = std::max(worst, tiles * ts.tm * ts.tn * (kk + k_ovh) * c.eff / w);
     }
-    if (worst < bestc) {
-      bestc = worst;
+    return worst;
+  };
+  // The paper's rule on each tile grid first (microseconds); a plan within
+  // 3% of its tile's lower bound is kept as it is.  Otherwise the search
+  // (tens of microseconds) runs on the tile with the best lower bound, and
+  // on the next one if that still leaves more than 3%.
+  std::vector<Piece> best;
+  double bestc = 1e300;
+  int bt = -1;
+  for (const Cand& c : cands) {
+    std::vector<Piece> v = partition_mm1(n, m, k, options(c.tile, false));
+    const double cs = cost(v, c);
+    if (cs < bestc) {
+      bestc = cs;
       best = std::move(v);
-      bt = t;
+      bt = c.tile;
+    }
+  }
+  double best_lb = 1e300;
+  for (const Cand& c : cands)
+    if (c.tile == bt) best_lb = c.lb;
+  // the search costs tens to hundreds of microseconds of host time: run it
+  // when the busiest processor's estimated time above the bound exceeds
+  // min_gain_s (padded element-steps at about 8.5e11 a second per processor
+  // for bf16x3 on matrix cores, half that for bf16x6, a fifth for float32)
+  const double rate = prec == PREC_BF16X6 ? 4.2e11 : (prec == PREC_FP32 ? 1.6e11 : 8.5e11);
+  if (bestc > 1.03 * best_lb && (bestc - best_lb) / rate > min_gain_s) {
+    std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.lb < b.lb; });
+    for (size_t i = 0; i < cands.size() && i < 2; ++i) {
+      if (cands[i].lb >= bestc) break;
+      std::vector<Piece> v = partition_mm1(n, m, k, options(cands[i].tile, true));
+      const double cs = cost(v, cands[i]);
+      if (cs < bestc) {
+        bestc = cs;
+        best = std::move(v);
+        bt = cands[i].tile;
+      }
+      if (bestc <= 1.03 * cands[i].lb) break;
     }
   }
   *tile_out = bt;
@@ -429,7 +472,8 @@ std::vector<Piece> ring_partition(int64_t n, int64_t m, int64_t k, int p, int pr
 
 // Host part of a semiring MM plan: partition, tile choice, work lists.
 void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
-                  int num_cus, DevPlan* np, double kcut_cost, const double* weights, int force_tile) {
+                  int num_cus, DevPlan* np, double kcut_cost, const double* weights, int force_tile,
+                  double search_min_gain_s) {
   const bool is_bool = sr == PACO_SR_OR_AND_B1;
   const int64_t mu = is_bool ? words(m) : m, ku = is_bool ? words(k) : k;
   const int fam = sr == PACO_SR_PLUS_TIMES_F32 ? 2 : (is_bool ? 1 : 0);
@@ -532,7 +576,7 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
       if (kcut_cost <= 0) kcut_cost = 1.0;
       kcut_cost_used = kcut_cost;
       const int forced = force_tile >= 0 ? force_tile : env_tile(tile_env, 5, -1);
-      pcs = ring_partition(n, m, k, p, prec, kcut_cost, weights, forced, &tile);
+      pcs = ring_partition(n, m, k, p, prec, kcut_cost, weights, forced, &tile, search_min_gain_s);
     } else {
       if (p <= 0) p = num_cus;
       if (kcut_cost <= 0) po.kcut_cost = 1.0;
@@ -897,7 +941,7 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
       trim_plans(ctx);
       std::unique_ptr<DevPlan> np(new DevPlan());
       make_mm_plan((int)d->sr, z.n, z.m, z.k, part, p, d->grid_split_k, z.prec, ctx->num_cus, np.get(), kc,
-                   weights, force_tile);
+                   weights, force_tile, ctx->search_min_gain);
       st = upload_plan(ctx, np.get());
       if (st != PACO_OK) return st;
       dp = np.get();
@@ -927,7 +971,7 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
       }
       std::unique_ptr<HostTables> nt(new HostTables());
       make_mm_plan((int)d->sr, z.n, z.m, z.k, part, p, d->grid_split_k, z.prec, ctx->num_cus, &nt->plan, kc,
-                   weights, force_tile);
+                   weights, force_tile, ctx->search_min_gain);
       pack_tables(nt.get());
       ht = nt.get();
       ctx->host_plans[key] = std::move(nt);

@@ -14,6 +14,7 @@
 
 #include "ctx.h"
 #include "device_types.h"
+#include "kernels.h"
 
 namespace paco {
 
@@ -39,7 +40,7 @@ double batch_weight(const BatchReq& r) {
 namespace {
 
 void split_rec(const std::vector<BatchReq>& reqs, const std::vector<int>& ids, size_t a, size_t b, int p0, int p1,
-               const std::vector<double>& w, std::vector<TaggedPiece>& out) {
+               const std::vector<double>& w, int tile, std::vector<TaggedPiece>& out) {
   if (b <= a) return;
   const int P = p1 - p0;
   if (b - a == 1 || P == 1) {
@@ -50,8 +51,13 @@ void split_rec(const std::vector<BatchReq>& reqs, const std::vector<int>& ids, s
       po.kcut_cost = default_kcut_cost(r.sr);
       const int g = batch_group(r);
       if (g == G_BOOL) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
-      else if (g <= G_RING_X6) { po.q[0] = 16; po.q[1] = 16; po.q[2] = 32; }
-      std::vector<Piece> pcs = partition_mm1(r.n, r.m, r.k, po);
+      std::vector<Piece> pcs;
+      if (g <= G_RING_X6 && tile >= 0) {
+        int t = tile;
+        pcs = ring_partition(r.n, r.m, r.k, P, r.prec, po.kcut_cost, nullptr, tile, &t, 2e-4);
+      } else {
+        pcs = partition_mm1(r.n, r.m, r.k, po);
+      }
       for (Piece& pc : pcs) {
         if (pc.empty()) continue;
         TaggedPiece t{pc, ids[a], p0 + pc.proc};
@@ -87,8 +93,33 @@ void split_rec(const std::vector<BatchReq>& reqs, const std::vector<int>& ids, s
   for (size_t i = a; i < c; ++i) wl += w[ids[i]];
   int pl = (int)std::llround(P * wl / tot);
   pl = std::min(std::max(pl, 1), P - 1);
-  split_rec(reqs, ids, a, c, p0, p0 + pl, w, out);
-  split_rec(reqs, ids, c, b, p0 + pl, p1, w, out);
+  split_rec(reqs, ids, a, c, p0, p0 + pl, w, tile, out);
+  split_rec(reqs, ids, c, b, p0 + pl, p1, w, tile, out);
+}
+
+// Tile of a ring group: the shape whose padded work over the group's
+// requests (each whole, n and m rounded up to the tile, weighted by the
+// tile's relative cost per element) is least.
+int group_ring_tile(const std::vector<BatchReq>& reqs, const std::vector<int>& ids, int prec) {
+  const int cand[4] = {RING_T256x256, RING_T256x128, RING_T128x128, RING_T128x64};
+  const double eff[4] = {1.0, 1.1, 1.25, 1.6};
+  int best = RING_T256x128;
+  double bestc = 1e300;
+  for (int c = 0; c < 4; ++c) {
+    if (cand[c] == RING_T256x256 && prec == PREC_BF16X6) continue;
+    const RingTileShape ts = ring_tile_shape(cand[c], prec);
+    double tot = 0;
+    for (int i : ids) {
+      const BatchReq& r = reqs[i];
+      tot += (double)((r.n + ts.tm - 1) / ts.tm * ts.tm) * (double)((r.m + ts.tn - 1) / ts.tn * ts.tn) *
+             (double)r.k * eff[c];
+    }
+    if (tot < bestc) {
+      bestc = tot;
+      best = cand[c];
+    }
+  }
+  return best;
 }
 
 }  // namespace
@@ -143,8 +174,12 @@ BatchSplit batch_partition(const std::vector<BatchReq>& reqs, int p) {
   int cur = 0;
   for (int g = 0; g < G_COUNT; ++g) {
     bs.g0[g] = cur;
+    bs.tile[g] = -1;
     if (!ids[g].empty()) {
-      split_rec(reqs, ids[g], 0, ids[g].size(), cur, cur + cnt[g], w, bs.pieces);
+      if (g <= G_RING_X6)
+        bs.tile[g] = group_ring_tile(reqs, ids[g], g == G_RING_FP32 ? PREC_FP32 : (g == G_RING_X3 ? PREC_BF16X3
+                                                                                                   : PREC_BF16X6));
+      split_rec(reqs, ids[g], 0, ids[g].size(), cur, cur + cnt[g], w, bs.tile[g], bs.pieces);
       cur += cnt[g];
     }
     bs.g1[g] = cur;

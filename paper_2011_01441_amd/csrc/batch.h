@@ -27,6 +27,7 @@ double batch_weight(const BatchReq& r);
 
 struct BatchSplit {
   int g0[G_COUNT], g1[G_COUNT];          // processor range of each group
+  int tile[G_COUNT];                     // ring groups: the kernel tile the group runs; else -1
   std::vector<TaggedPiece> pieces;       // prob = request index, wg = processor
 };
 
@@ -35,8 +36,9 @@ struct BatchSplit {
 // Within a group the request list (in arrival order) is split recursively
 // into two parts of about equal weight and the processors in the ratio of
 // the parts' weights; a request left alone with several processors is
-// partitioned with MM-1-Piece over them, requests left on one processor
-// run there whole.
+// partitioned with MM-1-Piece over them (ring requests on the group's tile
+// grid, the tile chosen first from the group's requests), requests left on
+// one processor run there whole.
 BatchSplit batch_partition(const std::vector<BatchReq>& reqs, int p);
 
 }  // namespace paco

@@ -53,6 +53,7 @@ struct paco_ctx_s {
   hipStream_t stream = nullptr;
   hipEvent_t switch_ev = nullptr;   // orders work across a change of stream (paco_set_stream)
   int num_cus = 0;
+  double search_min_gain = 2e-5;   // ring plans: see ring_partition (a server's context plans every request anew)
   uint64_t* stamps = nullptr;    // paco_set_piece_stamps: per-processor timestamps of semiring MM calls
   int32_t stamp_cap = 0;
   std::vector<double> weights;   // processor throughputs for default-p ring calls (paco_set_processor_weights)
@@ -98,8 +99,12 @@ paco_status ensure_ws(paco_ctx ctx, uint64_t bytes);
 int choose_int_tile(const std::vector<Piece>& pcs);
 int choose_bool_tile(const std::vector<Piece>& pcs);
 int choose_ring_tile(const std::vector<Piece>& pcs, int prec);
+// MM-1-Piece of a ring product on the matrix-core kernel's tile grid (the
+// tile chosen, or the forced one); the dimension search runs when it may
+// save more than min_gain_s of kernel time (plans of library calls are
+// cached per shape; the server plans every request anew).
 std::vector<Piece> ring_partition(int64_t n, int64_t m, int64_t k, int p, int prec, double kcut_cost,
-                                  const double* weights, int force_tile, int* tile_out);
+                                  const double* weights, int force_tile, int* tile_out, double min_gain_s = 2e-5);
 paco_status verify_sampled(paco_ctx ctx, int64_t n, int64_t m, int64_t k, const float* A, int64_t lda,
                            const float* B, int64_t ldb, const float* C, int64_t ldc, int rows,
                            uint64_t seed, paco_mm_result* res);
@@ -109,7 +114,7 @@ int auto_precision(int64_t k);
 bool ring_vec_ok(const void* A, int64_t lda, const void* B, int64_t ldb, int64_t m, int64_t k);
 void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
                   int num_cus, DevPlan* np, double kcut_cost, const double* weights = nullptr,
-                  int force_tile = -1);
+                  int force_tile = -1, double search_min_gain_s = 2e-5);
 double default_kcut_cost(int sr);
 double plan_kcut_cost(int sr);
 // The semiring MM call; force_tile >= 0 fixes the kernel tile (tuning).

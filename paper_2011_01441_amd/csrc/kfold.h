@@ -94,62 +94,6 @@ __device__ __forceinline__ void fold_tile(const ProbRef& pr, const RedTile& tl, 
   }
 }
 
-// The same fold with every load of up to UN units per thread in flight at
-// once (a fused fold runs in one workgroup, so its latency is the cost).
-template <class R, int VEC, int NT, int UN>
-__device__ __forceinline__ void fold_tile_wide(const ProbRef& pr, const RedTile& tl, const RedSrc* __restrict__ srcs,
-                                               const typename R::T* __restrict__ ws) {
-  using T = typename R::T;
-  const Problem P = uni(get_prob(pr, uni(tl.prob)));
-  const int i0 = uni(tl.i0), i1 = uni(tl.i1), j0 = uni(tl.j0), j1 = uni(tl.j1);
-  const int s0 = uni(tl.s0), s1 = uni(tl.s1);
-  T* C = (T*)P.C;
-  const int wv = (j1 - j0 + VEC - 1) / VEC;
-  const int units = wv * (i1 - i0);
-  for (int ub = 0; ub < units; ub += NT * UN) {
-    T v[UN][VEC];
-    T* cp[UN];
-    int iu[UN], ju[UN];
-    bool live[UN];
-#pragma unroll
-    for (int a = 0; a < UN; ++a) {
-      const int u = ub + a * NT + (int)threadIdx.x;
-      live[a] = u < units;
-      const int uu = live[a] ? u : 0;
-      iu[a] = i0 + uu / wv;
-      ju[a] = j0 + (uu % wv) * VEC;
-      cp[a] = C + (int64_t)iu[a] * P.ldc + ju[a];
-      if (live[a]) load_vec<T, VEC>(cp[a], v[a]);
-    }
-    for (int s = s0; s < s1; s += 2) {   // two sources of every unit in flight, folded in order
-      const bool two = s + 1 < s1;
-      const RedSrc S0 = srcs[s];
-      const RedSrc S1 = srcs[two ? s + 1 : s];
-      T x0[UN][VEC], x1[UN][VEC];
-#pragma unroll
-      for (int a = 0; a < UN; ++a) {
-        if (!live[a]) continue;
-        load_vec<T, VEC>(ws + S0.off + (int64_t)(iu[a] - S0.r0) * S0.ld + (ju[a] - S0.c0), x0[a]);
-        if (two) load_vec<T, VEC>(ws + S1.off + (int64_t)(iu[a] - S1.r0) * S1.ld + (ju[a] - S1.c0), x1[a]);
-      }
-#pragma unroll
-      for (int a = 0; a < UN; ++a) {
-        if (!live[a]) continue;
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) v[a][e] = R::op(v[a][e], x0[a][e]);
-        if (two)
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) v[a][e] = R::op(v[a][e], x1[a][e]);
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < UN; ++a)
-      if (live[a])
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) gstore(cp[a] + e, v[a][e]);
-  }
-}
-
 // Fused fold after work item `it` of a workgroup of NT threads: count the
 // item in each reduction cell it covers; fold the cells it completes.  A
 // plan without fused folding (pr.item_fold null) or an item covering no
@@ -179,9 +123,12 @@ __device__ __forceinline__ void fold_after_item(const ProbRef& pr, int it, const
     }
     __syncthreads();
     if (s_last) {
+      // the narrow fold: a wider one (every load of four units in flight)
+      // measured 2 us faster a call but cost the 64 x 64 (min,+) kernel a
+      // wave per SIMD (121 -> 130 registers), fused or not
       const RedTile tl = pr.fold_tiles[cell];
-      if (pr.fold_vec == 4) fold_tile_wide<R, 4, NT, 4>(pr, tl, pr.fold_srcs, ws);
-      else fold_tile_wide<R, 1, NT, 8>(pr, tl, pr.fold_srcs, ws);
+      if (pr.fold_vec == 4) fold_tile<R, 4, NT>(pr, tl, pr.fold_srcs, ws);
+      else fold_tile<R, 1, NT>(pr, tl, pr.fold_srcs, ws);
     }
     __syncthreads();
   }

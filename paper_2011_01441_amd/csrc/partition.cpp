@@ -28,7 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <deque>
-#include <map>
+#include <unordered_map>
 
 namespace paco {
 
@@ -113,16 +113,21 @@ struct TileSearch {
     int64_t len[3];
     int p0, P;
     bool face;
-    bool operator<(const Key& b) const {
-      if (len[0] != b.len[0]) return len[0] < b.len[0];
-      if (len[1] != b.len[1]) return len[1] < b.len[1];
-      if (len[2] != b.len[2]) return len[2] < b.len[2];
-      if (p0 != b.p0) return p0 < b.p0;
-      if (P != b.P) return P < b.P;
-      return face < b.face;
+    bool operator==(const Key& b) const {
+      return len[0] == b.len[0] && len[1] == b.len[1] && len[2] == b.len[2] && p0 == b.p0 && P == b.P &&
+             face == b.face;
     }
   };
-  std::map<Key, std::pair<double, int>> memo;
+  struct KeyHash {
+    size_t operator()(const Key& k) const {
+      uint64_t h = 1469598103934665603ull;
+      auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+      mix((uint64_t)k.len[0]); mix((uint64_t)k.len[1]); mix((uint64_t)k.len[2]);
+      mix((uint64_t)(uint32_t)k.p0 << 32 | (uint32_t)k.P); mix(k.face);
+      return (size_t)h;
+    }
+  };
+  std::unordered_map<Key, std::pair<double, int>, KeyHash> memo;
 
   double leaf(const int64_t len[3], bool face, int p0) const {
     if (len[0] <= 0 || len[1] <= 0 || len[2] <= 0) return 0.0;

@@ -229,7 +229,7 @@ paco_status launch_batch(paco_server s, Batch& b, std::vector<ReqState*>& rs, st
     gp[g].h = build_plan(tp, nwg, false, geom, temp_base);
     temp_base += (gp[g].h.temp_elems + 63) / 64 * 64;
     if (g <= G_RING_X6) {
-      gp[g].tile = choose_ring_tile(kpcs, g == G_RING_FP32 ? PREC_FP32 : (g == G_RING_X3 ? PREC_BF16X3 : PREC_BF16X6));
+      gp[g].tile = bs.tile[g];
       for (int i : gp[g].reqs) {
         const paco_request& q = rs[i]->r;
         if (!ring_vec_ok(q.A, q.lda ? q.lda : q.k, q.B, q.ldb ? q.ldb : q.m, q.m, q.k)) gp[g].vec = false;
@@ -450,6 +450,9 @@ extern "C" paco_status paco_server_create(paco_ctx ctx, const paco_server_opts* 
     return st;
   }
   s->p = s->o.p > 0 ? s->o.p : s->ctx->num_cus;
+  // every request is planned anew (one-off shapes): the tile search of a
+  // ring plan runs only where it may save 0.2 ms, in both modes
+  s->ctx->search_min_gain = 2e-4;
   bool ok = hipStreamCreateWithFlags(&s->main, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&s->ready, hipEventDisableTiming) == hipSuccess;
   for (int g = 0; g < G_COUNT && ok; ++g)

@@ -54,11 +54,21 @@ def test_batch_pieces_do_not_overlap_within_a_request():
         assert (cube == 1).all()
 
 
-def test_single_large_request_gets_all_processors_like_mm1piece(monkeypatch):
-    monkeypatch.setenv("PACO_KCUT_COST", "1")   # the paper's longest-dimension rule
+def test_single_large_request_gets_all_processors_like_mm1piece():
+    # a ring request alone gets every processor and the library call's plan:
+    # MM-1-Piece on the 256 x 256 tile grid, one output tile 8192 deep each
     pieces = P.batch_partition([dict(n=2048, m=1024, k=65536, semiring="ring",
                                      precision="bf16x3")], 256)
     assert len(pieces) == 256 and len({pc["proc"] for pc in pieces}) == 256
+    ext = {(pc["n1"] - pc["n0"], pc["m1"] - pc["m0"], pc["k1"] - pc["k0"]) for pc in pieces}
+    assert ext == {(256, 256, 8192)}
+    items, *_ = P.plan_export(2048, 1024, 65536, "ring", p=256, precision="bf16x3")
+    assert ext == {tuple(e) for e in (items[:, [2, 4, 6]] - items[:, [1, 3, 5]]).tolist()}
+
+
+def test_single_integer_request_keeps_the_paper_rule(monkeypatch):
+    monkeypatch.setenv("PACO_KCUT_COST", "1")   # the paper's longest-dimension rule
+    pieces = P.batch_partition([dict(n=2048, m=1024, k=65536, semiring="minplus")], 256)
     ext = {(pc["n1"] - pc["n0"], pc["m1"] - pc["m0"], pc["k1"] - pc["k0"]) for pc in pieces}
     assert ext == {(512, 1024, 1024)}
 
