@@ -101,3 +101,34 @@ def test_c3_strassen_pbfs_sampled(ctx):
     den = float(np.linalg.norm(A.astype(np.float64))) * float(np.linalg.norm(B.astype(np.float64)))
     print(f"  normwise 2^{math.log2(num / den):.1f}", flush=True)
     assert num / den <= 2.0 ** -16
+
+
+@pytest.mark.parametrize("p", [97, 200, 251])
+def test_c1_arbitrary_p_sampled(ctx, p):
+    """C1 over a prime and other non-power-of-two processor counts: the
+    tile-grid MM-1-Piece plan (its k-cuts and faces differ from p = 256)
+    stays within the bound on rows the oracle computes one by one."""
+    print(f"case: C1 bf16x3 p={p}, sampled rows", flush=True)
+    A, B = workloads.ring_operands(2048, 1024, 65536, seed=0)
+    Ad, Bd = dev(A), dev(B)
+    rows = sample_rows(2048, 6, p)
+    C64, S = oracle.ring_f64(A, B, rows=rows, with_abs=True)
+    C, res = ctx.semiring_mm(Ad, Bd, "ring", precision="bf16x3", p=p, return_result=True)
+    assert res["p"] == p and res["n_pieces"] <= p
+    Cr = C[torch.from_numpy(rows).to(DEV)].cpu().numpy().astype(np.float64)
+    err = np.max(np.abs(Cr - C64) / S)
+    print(f"  max rel 2^{math.log2(err):.1f}, faces {res['n_kcuts']}", flush=True)
+    assert err <= 2.0 ** -20
+
+
+@pytest.mark.parametrize("p", [7, 97, 200, 251])
+def test_ring_arbitrary_p_small_integers_exact(ctx, p):
+    """Small integers make every partial sum exact: at any p the tile-grid
+    plan (ragged sizes, k-cuts, faces folded in ascending k) gives the
+    oracle's result bit for bit."""
+    n, m, k = 700, 530, 3000
+    print(f"case: ring small integers {n}x{m}x{k} p={p}", flush=True)
+    A, B = workloads.small_int_operands(n, m, k, seed=p)
+    for prec in ("bf16x3", "fp32"):
+        C = ctx.semiring_mm(dev(A), dev(B), "ring", precision=prec, p=p)
+        assert np.array_equal(C.cpu().numpy().astype(np.float64), oracle.ring_f64(A, B)), prec
