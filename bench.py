@@ -466,6 +466,10 @@ def config_summary(torch, P, ctx, label, name, steps):
     one = timed(torch, lambda: call(ctx, w, Ad, Bd, C), 1)
     for _ in range(max(3, min(2000, int(math.ceil(0.2 / max(one, 1e-6)))))):
         call(ctx, w, Ad, Bd, C)
+    # at least `steps` calls and about 0.1 s of them (microsecond-scale
+    # calls would otherwise be timed over a few hundred microseconds)
+    one = timed(torch, lambda: call(ctx, w, Ad, Bd, C), 3)
+    steps = max(steps, min(4000, int(math.ceil(0.1 / max(one, 1e-6)))))
     ms = timed(torch, lambda: call(ctx, w, Ad, Bd, C), steps) * 1e3
     ctx.timing(True)
     timed(torch, lambda: call(ctx, w, Ad, Bd, C), steps)
@@ -474,7 +478,7 @@ def config_summary(torch, P, ctx, label, name, steps):
     kern_ms = tm["main_ms"] / max(tm["launches"], 1)
     work, unit, bound, peak = algorithmic(w, prec)
     achieved = work / (kern_ms * 1e-3) / 1e12
-    out = {"workload": name, "desc": w["desc"], "ms_per_step": round(ms, 4),
+    out = {"workload": name, "desc": w["desc"], "ms_per_step": round(ms, 4), "steps": steps,
            "value": round(classic_ops(w) / (ms * 1e-3) / 1e9, 3), "unit": "GOP/s",
            "roofline": {"kernel": {"strassen": "k_ring", "minplus": "k_semiring_int", "maxplus": "k_semiring_int",
                                    "bool": "k_semiring_bool"}[w["kind"]],

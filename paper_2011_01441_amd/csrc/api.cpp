@@ -505,10 +505,12 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
       // leaves each SIMD one wave to hide latency with, so a processor is a
       // workgroup slot: each candidate tile is tried with p = CUs x (its
       // resident workgroups per CU) -- when the problem gives every slot a
-      // few tiles -- and with four times as many pieces as slots, which the
-      // hardware dispatcher hands to slots as they free up (one piece per
-      // slot measured about 15% slower: the slots do not run at one speed,
-      // the XCD clocks alone differ by 3%).  Unless the caller fixed it, the
+      // few tiles -- and with four or sixteen times as many pieces as
+      // slots, which the hardware dispatcher hands to slots as they free up
+      // (the slots do not run at one speed, the XCD clocks alone differ by
+      // 3%: on (min,+) 8192^3 one, four and sixteen pieces per slot measured
+      // 25.96, 22.65 and 21.64 ms, the factors 1.2 / 1.045 / 1 below, the
+      // last equal to the tile grid's 16384 workgroups).  Unless the caller fixed it, the
       // k-cut cost is tried at 1 (the paper's rule), 4, 16 and 64.  The
       // plan with the shortest estimated time wins: the worst piece's
       // padded tiles, each costing its k-range plus a fixed
@@ -542,7 +544,7 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
           occ = std::min(std::max(occ, 1), 8);
           const double tile_work = (double)tm_ * tn_ * 256;   // one tile, 256 deep
           const int slots = (occ > 1 && work >= (double)num_cus * occ * 4 * tile_work) ? num_cus * occ : num_cus;
-          for (int f : {1, 4}) {
+          for (int f : {1, 4, 16}) {
             const int pt = slots * f;
             if (f > 1 && work < (double)pt * 4 * tile_work) continue;
             if (pt > 65536) continue;
@@ -559,7 +561,7 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
             }
             const double rounds = (double)pt / slots;
             const double cost = worst * ((double)slots / num_cus) * rounds * (fam == 0 ? ei[c] : eb[c]) /
-                                    rate_cu * (f == 1 ? 1.15 : 1.0) +
+                                    rate_cu * (f == 1 ? 1.2 : (f == 4 ? 1.045 : 1.0)) +
                                 temps * 8.0 / 5e12;
             if (cost < bestc) {
               bestc = cost;
