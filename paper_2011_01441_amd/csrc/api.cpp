@@ -471,6 +471,19 @@ std::vector<Piece> ring_partition(int64_t n, int64_t m, int64_t k, int p, int pr
 }
 
 // Host part of a semiring MM plan: partition, tile choice, work lists.
+// Relative time of f pieces per workgroup slot of a VALU plan: with one
+// piece per slot the slowest slot sets the end, with more the dispatcher
+// evens out the slots' speeds.
+static double slot_spread(int f) {
+  switch (f) {
+    case 1: return 1.2;
+    case 2: return 1.1;
+    case 4: return 1.045;
+    case 8: return 1.02;
+    default: return 1.0;
+  }
+}
+
 void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
                   int num_cus, DevPlan* np, double kcut_cost, const double* weights, int force_tile,
                   double search_min_gain_s) {
@@ -505,7 +518,7 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
       // leaves each SIMD one wave to hide latency with, so a processor is a
       // workgroup slot: each candidate tile is tried with p = CUs x (its
       // resident workgroups per CU) -- when the problem gives every slot a
-      // few tiles -- and with four or sixteen times as many pieces as
+      // few tiles -- and with two to sixteen times as many pieces as
       // slots, which the hardware dispatcher hands to slots as they free up
       // (the slots do not run at one speed, the XCD clocks alone differ by
       // 3%: on (min,+) 8192^3 one, four and sixteen pieces per slot measured
@@ -517,6 +530,9 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
       // prologue/epilogue overhead, at the tile's measured rate per compute
       // unit shared by the workgroups on it, times the rounds of pieces per
       // slot, plus the temporary faces written and read back at HBM speed.
+      // (Two and eight pieces per slot, between the measured points, take
+      // 1.1 and 1.02; on boolean 8192^3 two pieces per slot of the 512 x 32
+      // word tile measured 0.593 ms of kernel time against 0.614 for one.)
       // These kernels stream about 8 elements per byte, so a k-cut also
       // costs L2 reuse (concurrent pieces no longer walk k in step); the
       // overhead term and the face traffic stand for that.
@@ -544,9 +560,11 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
           occ = std::min(std::max(occ, 1), 8);
           const double tile_work = (double)tm_ * tn_ * 256;   // one tile, 256 deep
           const int slots = (occ > 1 && work >= (double)num_cus * occ * 4 * tile_work) ? num_cus * occ : num_cus;
-          for (int f : {1, 4, 16}) {
+          for (int f : {1, 2, 4, 8, 16}) {
             const int pt = slots * f;
-            if (f > 1 && work < (double)pt * 4 * tile_work) continue;
+            // more pieces than slots only while each keeps a tile's worth of
+            // work (the per-tile overhead term prices smaller ones)
+            if (f > 1 && work < (double)pt * tile_work) continue;
             if (pt > 65536) continue;
             std::vector<Piece> v = part_for(pt);
             std::vector<double> load(pt, 0.0);   // per processor (multi-piece: several pieces)
@@ -561,7 +579,7 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
             }
             const double rounds = (double)pt / slots;
             const double cost = worst * ((double)slots / num_cus) * rounds * (fam == 0 ? ei[c] : eb[c]) /
-                                    rate_cu * (f == 1 ? 1.2 : (f == 4 ? 1.045 : 1.0)) +
+                                    rate_cu * slot_spread(f) +
                                 temps * 8.0 / 5e12;
             if (cost < bestc) {
               bestc = cost;

@@ -128,26 +128,32 @@ __global__ __launch_bounds__(kThreads) void k_semiring_int(ProbRef pr, const Wor
           }
           __syncthreads();
           if (kk + kBK < W.k1) load(kk + kBK);
-#pragma unroll 1
-          for (int l0 = 0; l0 < kBK; l0 += kLChunk)
+          // chunks wholly past the piece's k-range hold only padding, whose
+          // products never win the fold: a piece's last step stops after the
+          // chunk that holds k1 - 1 (at least one chunk runs: kk < k1)
+          const int lim = W.k1 - kk < kBK ? W.k1 - kk : kBK;
+          int l0 = 0;
+          do {
 #pragma unroll
-          for (int l = l0; l < l0 + kLChunk; ++l) {
-            T a[RM], b[RN];
+            for (int l = l0; l < l0 + kLChunk; ++l) {
+              T a[RM], b[RN];
 #pragma unroll
-            for (int h = 0; h < HM; ++h) {
-              a[h] = As[buf][l][ty * HM + h];
-              a[HM + h] = As[buf][l][TM / 2 + ty * HM + h];
+              for (int h = 0; h < HM; ++h) {
+                a[h] = As[buf][l][ty * HM + h];
+                a[HM + h] = As[buf][l][TM / 2 + ty * HM + h];
+              }
+#pragma unroll
+              for (int h = 0; h < HN; ++h) {
+                b[h] = Bs[buf][l][tx * HN + h];
+                b[HN + h] = Bs[buf][l][TN / 2 + tx * HN + h];
+              }
+#pragma unroll
+              for (int i = 0; i < RM; ++i)
+#pragma unroll
+                for (int j = 0; j < RN; ++j) acc[i][j] = Op::add(acc[i][j], Op::mul(a[i], b[j]));
             }
-#pragma unroll
-            for (int h = 0; h < HN; ++h) {
-              b[h] = Bs[buf][l][tx * HN + h];
-              b[HN + h] = Bs[buf][l][TN / 2 + tx * HN + h];
-            }
-#pragma unroll
-            for (int i = 0; i < RM; ++i)
-#pragma unroll
-              for (int j = 0; j < RN; ++j) acc[i][j] = Op::add(acc[i][j], Op::mul(a[i], b[j]));
-          }
+            l0 += kLChunk;
+          } while (l0 < lim);
           buf ^= 1;
         }
         // epilogue

@@ -98,7 +98,7 @@ extern "C" paco_status paco_tune(paco_ctx ctx, const paco_mm_desc* d, paco_tune_
     for (int t = 0; t < (is_bool ? 4 : kIntTiles); ++t) {
       int occ = is_bool ? bool_occupancy(t) : int_occupancy((int)d->sr, t);
       occ = std::min(std::max(occ, 1), 8);
-      for (int f : {1, 4, 16})
+      for (int f : {1, 2, 4, 8, 16})
         for (double kc : {1.0, 16.0, 64.0})
           if (C * occ * f <= 65536) cands.push_back({(int)PACO_PART_PACO, C * occ * f, t, kc, false});
     }
