@@ -6,7 +6,8 @@
 // Row i of C is the OR of the rows l of B for which bit l of row i of A is
 // set; with A's bit broadcast to a full-word mask (one bit-field extract per
 // row and bit, shared by all of the thread's C words) every (row, bit, word)
-// step is a single and-or.  A cuboid's C face is swept in TM-row by TNW-word
+// step is a single and-or (a thread's 4 x 16 register tile: one extract per
+// sixteen and-ors).  A cuboid's C face is swept in TM-row by TNW-word
 // tiles; its k-range (bits, cut on multiples of 32) is folded 64 bits per
 // step through double-buffered LDS.
 #include "kcommon.h"
@@ -162,13 +163,13 @@ int bool_occupancy(int tile) {
   hipError_t e = hipErrorInvalidValue;
   switch (tile) {
     case BOOL_T512x32W:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_bool<512, 32, 8, 8>, kThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_bool<512, 32, 4, 16>, kThreads, 0);
       break;
     case BOOL_T128x128W:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_bool<128, 128, 8, 8>, kThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_bool<128, 128, 4, 16>, kThreads, 0);
       break;
     case BOOL_T256x64W:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_bool<256, 64, 8, 8>, kThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_bool<256, 64, 4, 16>, kThreads, 0);
       break;
     case BOOL_T64x64W:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_bool<64, 64, 4, 4>, kThreads, 0);
@@ -194,13 +195,13 @@ hipError_t launch_semiring_bool(int tile, const ProbRef& pr, const WorkItem* ite
   uint32_t* w = (uint32_t*)ws;
   switch (tile) {
     case BOOL_T512x32W:
-      hipLaunchKernelGGL((k_semiring_bool<512, 32, 8, 8>), g, b, 0, s, pr, items, wg_off, nwg, xcd, w);
+      hipLaunchKernelGGL((k_semiring_bool<512, 32, 4, 16>), g, b, 0, s, pr, items, wg_off, nwg, xcd, w);
       break;
     case BOOL_T128x128W:
-      hipLaunchKernelGGL((k_semiring_bool<128, 128, 8, 8>), g, b, 0, s, pr, items, wg_off, nwg, xcd, w);
+      hipLaunchKernelGGL((k_semiring_bool<128, 128, 4, 16>), g, b, 0, s, pr, items, wg_off, nwg, xcd, w);
       break;
     case BOOL_T256x64W:
-      hipLaunchKernelGGL((k_semiring_bool<256, 64, 8, 8>), g, b, 0, s, pr, items, wg_off, nwg, xcd, w);
+      hipLaunchKernelGGL((k_semiring_bool<256, 64, 4, 16>), g, b, 0, s, pr, items, wg_off, nwg, xcd, w);
       break;
     case BOOL_T64x64W:
       hipLaunchKernelGGL((k_semiring_bool<64, 64, 4, 4>), g, b, 0, s, pr, items, wg_off, nwg, xcd, w);
