@@ -212,6 +212,22 @@ def timed(torch, fn, steps):
     return (time.perf_counter() - t0) / steps
 
 
+def second_round(torch, paco_fn, base_fn, steps, paco_ms, base_ms, base_env=None):
+    """Time PACO and its baseline once more, PACO first, and keep the faster
+    window of each: the first PACO window runs right after warm-up and the
+    first baseline window after the baseline's own autotuning calls, so a
+    single window of each would favour whichever ran later."""
+    p2 = timed(torch, paco_fn, steps) * 1e3
+    if base_env:
+        os.environ[base_env[0]] = base_env[1]
+    try:
+        b2 = timed(torch, base_fn, steps) * 1e3
+    finally:
+        if base_env:
+            del os.environ[base_env[0]]
+    return min(paco_ms, p2), min(base_ms, b2), p2, b2
+
+
 def host_info():
     """CPU model and the cores this process may run on."""
     model = None
@@ -446,7 +462,8 @@ CONFIG_SET = [("C0", "minplus_c0"), ("C2a", "maxplus_c2a"), ("C2b", "bool_c2b"),
 
 
 def config_summary(torch, P, ctx, label, name, steps):
-    """One configuration: PACO step time, the dominant kernel's roofline
+    """One configuration: PACO step time (the faster of two windows that
+    alternate with the baseline's), the dominant kernel's roofline
     fraction, the autotuned tile grid (or, for Strassen, the classic product)
     on the same operands, and a parity verdict against the oracle (integer
     semirings: bit-exact on every output row, or on sampled rows for the
@@ -492,6 +509,9 @@ def config_summary(torch, P, ctx, label, name, steps):
         for _ in range(3):
             f()
         cms = timed(torch, f, steps) * 1e3
+        ms, cms, _, _ = second_round(torch, lambda: call(ctx, w, Ad, Bd, C), f, steps, ms, cms)
+        out["ms_per_step"] = round(ms, 4)
+        out["value"] = round(classic_ops(w) / (ms * 1e-3) / 1e9, 3)
         out["classic_ms"] = round(cms, 4)
         out["strassen_vs_classic"] = round(cms / ms, 4)
     else:
@@ -506,8 +526,13 @@ def config_summary(torch, P, ctx, label, name, steps):
                 if best is None or t < best[2]:
                     best = (tile, sk, t)
         os.environ[tile_env] = str(best[0])
-        gms = timed(torch, lambda: call(ctx, w, Ad, Bd, C, part="grid", split_k=best[1]), steps) * 1e3
+        gf = lambda: call(ctx, w, Ad, Bd, C, part="grid", split_k=best[1])
+        gms = timed(torch, gf, steps) * 1e3
         del os.environ[tile_env]
+        ms, gms, _, _ = second_round(torch, lambda: call(ctx, w, Ad, Bd, C), gf, steps, ms, gms,
+                                     (tile_env, str(best[0])))
+        out["ms_per_step"] = round(ms, 4)
+        out["value"] = round(classic_ops(w) / (ms * 1e-3) / 1e9, 3)
         out["grid_ms"] = round(gms, 4)
         out["grid_tile_split_k"] = [best[0], best[1]]
         out["paco_vs_grid"] = round(gms / ms, 4)
@@ -702,7 +727,9 @@ def main():
         for _ in range(3):
             f()
         cms = timed(torch, f, args.steps) * 1e3
-        classic = {"value": classic_ops(w) / (cms * 1e-3) / 1e9, "ms_per_step": round(cms, 4)}
+        pbest, cms, p2, _ = second_round(torch, lambda: call(ctx, w, Ad, Bd, C), f, args.steps, ms, cms)
+        classic = {"value": classic_ops(w) / (cms * 1e-3) / 1e9, "ms_per_step": round(cms, 4),
+                   "paco_ms_second_window": round(p2, 4), "paco_ms_compared": round(pbest, 4)}
         log(f"classic product: {cms:.3f} ms/step")
 
     # ---- plain tile grid (same microkernels), tile shape and split-k autotuned
@@ -713,8 +740,10 @@ def main():
         f = lambda: call(ctx, w, Ad, Bd, C, part="grid")
         f()
         gms = timed(torch, f, args.steps) * 1e3
+        pbest, gms, p2, _ = second_round(torch, lambda: call(ctx, w, Ad, Bd, C), f, args.steps, ms, gms)
         grid = {"value": classic_ops(w) / (gms * 1e-3) / 1e9, "ms_per_step": round(gms, 4),
                 "tile": None, "split_k": None,
+                "paco_ms_second_window": round(p2, 4), "paco_ms_compared": round(pbest, 4),
                 "partition": "output strips only" if w["kind"] == "dp1d" else "16 x 256 cube tiles"}
         log(f"grid: {gms:.3f} ms/step")
     elif not args.no_grid and w["kind"] != "strassen":
@@ -731,11 +760,14 @@ def main():
                 if best is None or t < best[2]:
                     best = (tile, sk, t)
         os.environ[tile_env] = str(best[0])
-        gms = timed(torch, lambda: call(ctx, w, Ad, Bd, C, part="grid", split_k=best[1]),
-                    args.steps) * 1e3
+        gf = lambda: call(ctx, w, Ad, Bd, C, part="grid", split_k=best[1])
+        gms = timed(torch, gf, args.steps) * 1e3
         del os.environ[tile_env]
+        pbest, gms, p2, _ = second_round(torch, lambda: call(ctx, w, Ad, Bd, C), gf, args.steps, ms, gms,
+                                         (tile_env, str(best[0])))
         grid = {"value": classic_ops(w) / (gms * 1e-3) / 1e9, "ms_per_step": round(gms, 4),
-                "tile": best[0], "split_k": best[1]}
+                "tile": best[0], "split_k": best[1],
+                "paco_ms_second_window": round(p2, 4), "paco_ms_compared": round(pbest, 4)}
         log(f"grid: {gms:.3f} ms/step (tile {best[0]}, split_k {best[1]})")
 
     balance = None
@@ -850,11 +882,11 @@ def main():
         "single_call": call_stats,
         "measured_peaks": peaks,
         "grid_baseline": grid,
-        "paco_vs_grid": round(grid["ms_per_step"] / ms, 4) if grid else None,
+        "paco_vs_grid": round(grid["ms_per_step"] / grid.get("paco_ms_compared", ms), 4) if grid else None,
         "graph_replay": graph,
         "classic_baseline": classic,
         "vendor_baseline": vendor,
-        "strassen_vs_classic": round(classic["ms_per_step"] / ms, 4) if classic else None,
+        "strassen_vs_classic": round(classic["ms_per_step"] / classic.get("paco_ms_compared", ms), 4) if classic else None,
         "error": err,
         "server": server,
         "configs": configs,
