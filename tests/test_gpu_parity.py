@@ -260,3 +260,43 @@ def test_ring_forced_tiles_exact(ctx, tile, prec, monkeypatch):
     A, B = workloads.small_int_operands(n, m, k, seed=tile + 3)
     C = host(ctx.semiring_mm(dev(A), dev(B), "ring", precision=prec, p=64))
     assert np.array_equal(C.astype(np.float64), oracle.ring_f64(A, B))
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("sr", ["minplus", "maxplus"])
+def test_int_ragged_k_steps(ctx, tile, sr, monkeypatch):
+    """Pieces whose k-range ends anywhere inside a 32-deep step (the kernel
+    stops a piece's last step after the 8-deep chunk holding k1 - 1): every
+    tile, k from 1 to 257, split-k grids of 1, 3 and 7 parts and the PACO
+    plan at p = 5; bit-exact."""
+    monkeypatch.setenv("PACO_INT_TILE", str(tile))
+    gen = workloads.minplus_operands if sr == "minplus" else workloads.maxplus_operands
+    ref_fn = oracle.minplus if sr == "minplus" else oracle.maxplus
+    n, m = 70, 90
+    for k in (1, 7, 8, 9, 33, 40, 257):
+        A, B = gen(n, m, k, seed=tile * 7 + k)
+        ref = ref_fn(A, B)
+        for sk in (1, 3, 7):
+            if sk > k:
+                continue
+            print(f"case: int ragged k tile {tile} {sr} k={k} split_k={sk}", flush=True)
+            got = host(ctx.semiring_mm(dev(A), dev(B), sr, part="grid", split_k=sk))
+            assert np.array_equal(got, ref), (k, sk)
+        print(f"case: int ragged k tile {tile} {sr} k={k} paco p=5", flush=True)
+        assert np.array_equal(host(ctx.semiring_mm(dev(A), dev(B), sr, p=5, kcut_cost=1.0)), ref), k
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+def test_bool_tiles_bit_exact(ctx, tile, monkeypatch):
+    """Every boolean tile shape (4 x 16 register tiles on the three wide
+    ones, 4 x 4 on 64 x 64 words) forced through PACO_BOOL_TILE, ragged
+    sizes, PACO and split-k grids: bit-exact."""
+    monkeypatch.setenv("PACO_BOOL_TILE", str(tile))
+    for (n, m, k, dens) in [(300, 1000, 777, 0.02), (513, 2080, 160, 0.05), (64, 31, 4100, 0.005)]:
+        _, _, ap, bp = workloads.bool_operands(n, m, k, density=dens, seed=tile + n)
+        ref = oracle.bool_packed(ap, bp, n, m, k)
+        Ad, Bd = dev(ap.view(np.int32)), dev(bp.view(np.int32))
+        for kw in ({}, {"part": "grid", "split_k": 1}, {"part": "grid", "split_k": 3}, {"p": 7, "kcut_cost": 1.0}):
+            print(f"case: bool tile {tile} {n}x{m}x{k} {kw}", flush=True)
+            got = host(ctx.semiring_mm(Ad, Bd, "bool", n=n, m=m, k=k, **kw)).view(np.uint32)
+            assert np.array_equal(got, ref), kw
