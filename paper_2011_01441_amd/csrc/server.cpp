@@ -78,10 +78,17 @@ struct ReqState {
   bool finished = false;
 };
 
+// Descriptor blobs up to this size are read by the kernels straight from
+// coherent pinned host memory (a handful of reads per workgroup), saving
+// the copy to device memory and its host call.
+constexpr size_t kZeroCopyBytes = 64 << 10;
+
 struct Slot {
   void* dev = nullptr;             // device descriptor buffer
   void* host = nullptr;            // pinned staging buffer
   size_t cap = 0;
+  void* zhost = nullptr;           // coherent pinned buffer of kZeroCopyBytes
+  void* zdev = nullptr;            // its device address
   hipEvent_t done = nullptr;       // last batch that used the slot
   bool used = false;
 };
@@ -261,8 +268,9 @@ paco_status launch_batch(paco_server s, Batch& b, std::vector<ReqState*>& rs, st
   Slot& sl = s->slots[s->next_slot];
   s->next_slot = (s->next_slot + 1) % kSlots;
   if (sl.used) (void)hipEventSynchronize(sl.done);   // its batch no longer reads the descriptors
-  if ((st = grow_slot(s, sl, tot)) != PACO_OK) return st;
-  char* hb = (char*)sl.host;
+  const bool zc = tot <= kZeroCopyBytes && sl.zdev;
+  if (!zc && (st = grow_slot(s, sl, tot)) != PACO_OK) return st;
+  char* hb = (char*)(zc ? sl.zhost : sl.host);
   for (int g = 0; g < G_COUNT; ++g) {
     if (gp[g].reqs.empty()) continue;
     Problem* pt = (Problem*)(hb + off[g].prob);
@@ -281,13 +289,21 @@ paco_status launch_batch(paco_server s, Batch& b, std::vector<ReqState*>& rs, st
     memcpy(hb + off[g].tiles, gp[g].h.tiles.data(), sizeof(RedTile) * gp[g].h.tiles.size());
     memcpy(hb + off[g].srcs, gp[g].h.srcs.data(), sizeof(RedSrc) * gp[g].h.srcs.size());
   }
-  hipError_t e = hipMemcpyAsync(sl.dev, sl.host, tot, hipMemcpyHostToDevice, s->main);
-  if (e == hipSuccess) e = hipEventRecord(s->ready, s->main);
-  char* db = (char*)sl.dev;
+  // Several kernel groups run side by side on their own streams, after the
+  // descriptor copy and before the batch's completion event on the main
+  // stream; a batch of one group (the usual case at light load) launches on
+  // the main stream itself: each cross-stream event pair costs tens of
+  // microseconds of host time, as much as the small requests' kernels.
+  int ngroups = 0;
+  for (int g = 0; g < G_COUNT; ++g) ngroups += gp[g].reqs.empty() ? 0 : 1;
+  const bool single = ngroups == 1;
+  hipError_t e = zc ? hipSuccess : hipMemcpyAsync(sl.dev, sl.host, tot, hipMemcpyHostToDevice, s->main);
+  if (e == hipSuccess && !single) e = hipEventRecord(s->ready, s->main);
+  char* db = (char*)(zc ? sl.zdev : sl.dev);
   for (int g = 0; g < G_COUNT && e == hipSuccess; ++g) {
     if (gp[g].reqs.empty()) continue;
-    hipStream_t gsm = s->gs[g];
-    e = hipStreamWaitEvent(gsm, s->ready, 0);
+    hipStream_t gsm = single ? s->main : s->gs[g];
+    if (!single) e = hipStreamWaitEvent(gsm, s->ready, 0);
     if (e != hipSuccess) break;
     ProbRef pr;
     memset(&pr, 0, sizeof pr);
@@ -310,8 +326,8 @@ paco_status launch_batch(paco_server s, Batch& b, std::vector<ReqState*>& rs, st
       e = launch_reduce(sr, pr, (const RedTile*)(db + off[g].tiles), (int)gp[g].h.tiles.size(),
                         (const RedSrc*)(db + off[g].srcs), s->ws, gsm, 1);
     }
-    if (e == hipSuccess) e = hipEventRecord(s->gdone[g], gsm);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s->main, s->gdone[g], 0);
+    if (e == hipSuccess && !single) e = hipEventRecord(s->gdone[g], gsm);
+    if (e == hipSuccess && !single) e = hipStreamWaitEvent(s->main, s->gdone[g], 0);
   }
   if (e == hipSuccess) e = hipEventRecord(b.ev, s->main);
   if (e == hipSuccess) e = hipEventRecord(sl.done, s->main);
@@ -458,7 +474,12 @@ extern "C" paco_status paco_server_create(paco_ctx ctx, const paco_server_opts* 
   for (int g = 0; g < G_COUNT && ok; ++g)
     ok = hipStreamCreateWithFlags(&s->gs[g], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&s->gdone[g], hipEventDisableTiming) == hipSuccess;
-  for (int i = 0; i < kSlots && ok; ++i) ok = hipEventCreateWithFlags(&s->slots[i].done, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < kSlots && ok; ++i) {
+    Slot& sl = s->slots[i];
+    ok = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
+         hipHostMalloc(&sl.zhost, kZeroCopyBytes, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+         hipHostGetDevicePointer(&sl.zdev, sl.zhost, 0) == hipSuccess;
+  }
   if (!ok) {
     paco_server_destroy(s);
     return PACO_ERR_HIP;
@@ -579,6 +600,7 @@ extern "C" paco_status paco_server_destroy(paco_server s) {
   for (int i = 0; i < kSlots; ++i) {
     if (s->slots[i].dev) (void)hipFree(s->slots[i].dev);
     if (s->slots[i].host) (void)hipHostFree(s->slots[i].host);
+    if (s->slots[i].zhost) (void)hipHostFree(s->slots[i].zhost);
     if (s->slots[i].done) (void)hipEventDestroy(s->slots[i].done);
   }
   if (s->ready) (void)hipEventDestroy(s->ready);
