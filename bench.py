@@ -624,7 +624,7 @@ def main():
     dev = torch.device("cuda:0")
     A, B, Ad, Bd = make_inputs(w, torch, dev)
     ctx = P.Context(0)
-    prec = w.get("prec", "int")
+    prec = w.get("prec", "bits" if w["kind"] == "bool" else "int")
     if w["kind"] == "bool":
         C = torch.empty((w["n"], (w["m"] + 31) // 32), dtype=torch.int32, device=dev)
     elif w["kind"] == "strassen":
