@@ -105,6 +105,9 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
     }
   }
   hp.fused = fuse == 1;
+  // about one tile per 1024 face elements, and the cells' sources
+  hp.tiles.reserve((size_t)(hp.temp_elems / 1024) + 64);
+  hp.srcs.reserve(4 * (size_t)hp.n_kcuts + 64);
   std::vector<std::vector<int32_t>> piece_cells(hp.fused ? pieces.size() : 0);
   for (auto& kv : temps_of) {
     const int prob = kv.first;
@@ -167,9 +170,10 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
           continue;
         }
         // split the cell into tiles of at most 256*vec columns and about
-        // 1024 elements (many workgroups: the fold is bandwidth-bound)
+        // 1024 elements: a 256-thread workgroup folds one or four elements
+        // per thread (many workgroups: the fold is bandwidth-bound)
         int64_t cw = std::min<int64_t>(j1 - j0, 256 * vec);
-        int64_t rh = std::max<int64_t>(1, (256 * vec) / cw);
+        int64_t rh = std::max<int64_t>(1, 1024 / cw);
         for (int64_t ii = i0; ii < i1; ii += rh)
           for (int64_t jj = j0; jj < j1; jj += cw) {
             RedTile t;

@@ -147,3 +147,25 @@ def test_server_forgets_polled_requests(ctx, pools):
     assert st["max_s"] == pytest.approx(lat[-1])
     assert np.array_equal(C.cpu().numpy(), oracle.minplus(a[:8, :8], b[:8, :8]))
     srv.close()
+
+
+def test_server_dispatch_paths(ctx, pools):
+    """The ways a batch reaches the GPU, each checked against the oracle:
+    a lone small request (one kernel group: the main stream, descriptors
+    read from pinned host memory), a lone (min,+) request whose descriptors
+    exceed 64 KiB (copied to device memory first), and one batch of both
+    kinds (a stream per kernel group, joined by events)."""
+    for shapes in ([("ring", 100, 100, 100)], [("minplus", 700, 700, 700)]):
+        print(f"case: server lone request {shapes[0]}", flush=True)
+        srv = P.Server(ctx)
+        runs = _run(srv, pools, shapes)
+        _check(pools, srv, runs)
+        srv.close()
+    print("case: server one mixed batch", flush=True)
+    srv = P.Server(ctx, window_s=0.2)
+    runs = _run(srv, pools, [("ring", 100, 100, 100), ("minplus", 700, 700, 700),
+                             ("ring", 640, 512, 700), ("minplus", 33, 47, 65)])
+    _check(pools, srv, runs)
+    st = srv.stats()
+    assert st["batches"] == 1 and st["completed"] == 4, st
+    srv.close()
