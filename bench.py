@@ -535,7 +535,13 @@ def config_summary(torch, P, ctx, label, name, steps):
         out["value"] = round(classic_ops(w) / (ms * 1e-3) / 1e9, 3)
         out["grid_ms"] = round(gms, 4)
         out["grid_tile_split_k"] = [best[0], best[1]]
+        out["grid_trials"] = (4 if w["kind"] == "bool" else 5) * 7
         out["paco_vs_grid"] = round(gms / ms, 4)
+        # the grid's own defaults, untuned: the largest tile, split-k only to
+        # fill the compute units
+        dms = timed(torch, lambda: call(ctx, w, Ad, Bd, C, part="grid"), steps) * 1e3
+        out["grid_default_ms"] = round(dms, 4)
+        out["paco_vs_grid_default"] = round(dms / ms, 4)
         if ms < 0.1:   # launch-bound: the same step replayed from a hipGraph
             rep = 50
             G = (ctx.graph(Ad, Bd, "bool", n=w["n"], m=w["m"], k=w["k"], C=C, repeat=rep) if w["kind"] == "bool"
@@ -765,9 +771,12 @@ def main():
         del os.environ[tile_env]
         pbest, gms, p2, _ = second_round(torch, lambda: call(ctx, w, Ad, Bd, C), gf, args.steps, ms, gms,
                                          (tile_env, str(best[0])))
+        dms = timed(torch, lambda: call(ctx, w, Ad, Bd, C, part="grid"), args.steps) * 1e3
         grid = {"value": classic_ops(w) / (gms * 1e-3) / 1e9, "ms_per_step": round(gms, 4),
                 "tile": best[0], "split_k": best[1],
-                "paco_ms_second_window": round(p2, 4), "paco_ms_compared": round(pbest, 4)}
+                "paco_ms_second_window": round(p2, 4), "paco_ms_compared": round(pbest, 4),
+                "trials": len(tiles) * 8,
+                "default_ms": round(dms, 4), "paco_vs_default": round(dms / pbest, 4)}
         log(f"grid: {gms:.3f} ms/step (tile {best[0]}, split_k {best[1]})")
 
     balance = None
