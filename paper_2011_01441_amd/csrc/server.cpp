@@ -476,9 +476,15 @@ extern "C" paco_status paco_server_create(paco_ctx ctx, const paco_server_opts* 
          hipEventCreateWithFlags(&s->gdone[g], hipEventDisableTiming) == hipSuccess;
   for (int i = 0; i < kSlots && ok; ++i) {
     Slot& sl = s->slots[i];
-    ok = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
-         hipHostMalloc(&sl.zhost, kZeroCopyBytes, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
-         hipHostGetDevicePointer(&sl.zdev, sl.zhost, 0) == hipSuccess;
+    ok = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
+    // without a coherent mapped buffer the slot copies every blob instead
+    if (ok && hipHostMalloc(&sl.zhost, kZeroCopyBytes, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+        hipHostGetDevicePointer(&sl.zdev, sl.zhost, 0) != hipSuccess) {
+      (void)hipHostFree(sl.zhost);
+      sl.zhost = sl.zdev = nullptr;
+    }
+    if (!sl.zhost) sl.zdev = nullptr;
+    (void)hipGetLastError();   // a failed optional allocation is not the next call's error
   }
   if (!ok) {
     paco_server_destroy(s);
