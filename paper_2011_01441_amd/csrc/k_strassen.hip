@@ -43,12 +43,16 @@ struct Vec {
   float v[VW];
 };
 
+typedef float f32x4nt __attribute__((ext_vector_type(4)));
+
+// every value is read once and written once per call, so 16-byte accesses
+// are non-temporal
 template <int VW>
 __device__ __forceinline__ Vec<VW> vload(const float* p) {
   Vec<VW> r;
   if constexpr (VW == 4) {
-    float4 x = *(const float4*)p;
-    r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
+    const f32x4nt x = __builtin_nontemporal_load((const f32x4nt*)p);
+    r.v[0] = x[0]; r.v[1] = x[1]; r.v[2] = x[2]; r.v[3] = x[3];
   } else if constexpr (VW == 2) {
     float2 x = *(const float2*)p;
     r.v[0] = x.x; r.v[1] = x.y;
@@ -61,7 +65,7 @@ __device__ __forceinline__ Vec<VW> vload(const float* p) {
 template <int VW>
 __device__ __forceinline__ void vstore(float* p, const Vec<VW>& r) {
   if constexpr (VW == 4) {
-    *(float4*)p = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+    __builtin_nontemporal_store((f32x4nt){r.v[0], r.v[1], r.v[2], r.v[3]}, (f32x4nt*)p);
   } else if constexpr (VW == 2) {
     *(float2*)p = make_float2(r.v[0], r.v[1]);
   } else {
