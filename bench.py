@@ -465,7 +465,7 @@ def config_summary(torch, P, ctx, label, name, steps):
     """One configuration: PACO step time (the faster of two windows that
     alternate with the baseline's), the dominant kernel's roofline
     fraction, the autotuned tile grid (or, for Strassen, the classic product)
-    on the same operands, and a parity verdict against the oracle (integer
+    on the same operands, and a parity check against the oracle (integer
     semirings: bit-exact on every output row, or on sampled rows for the
     8192^3 shape; Strassen: float64 normwise error of sampled rows)."""
     import oracle
