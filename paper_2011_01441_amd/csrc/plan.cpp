@@ -11,24 +11,101 @@
 #include "plan.h"
 
 #include <algorithm>
-#include <map>
+#include <numeric>
 
 namespace paco {
 
+namespace {
+
+// The cells of one problem's temporary faces: the overlay of the faces' row
+// boundaries rb and column boundaries cb; cell (r, c) lists the faces that
+// cover it, in ascending k, at list[start[r * Cn + c] .. start[r * Cn + c + 1]).
+// Flat arrays filled by counting: a server plans every lone request anew,
+// and per-cell containers cost more than the rest of the plan.
+struct Overlay {
+  std::vector<int64_t> rb, cb;
+  std::vector<int32_t> start, list;
+  size_t R = 0, Cn = 0;
+};
+
+// Sorted distinct values of v.  A partition's faces share few boundaries
+// (hundreds of values, a handful distinct): insertion into the short sorted
+// list beats sorting them all; past 64 distinct values, sort.
+void sorted_unique(std::vector<int64_t>& v) {
+  size_t d = 0;
+  for (size_t i = 0; i < v.size(); ++i) {
+    const int64_t x = v[i];
+    size_t at = std::lower_bound(v.begin(), v.begin() + d, x) - v.begin();
+    if (at < d && v[at] == x) continue;
+    if (d == 64) {
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+      return;
+    }
+    // v[i] is read already, and i >= d, so the shift only overwrites
+    // values that are in the sorted prefix or done with
+    for (size_t j = d; j > at; --j) v[j] = v[j - 1];
+    v[at] = x;
+    ++d;
+  }
+  v.resize(d);
+}
+
+void overlay(const std::vector<TaggedPiece>& pieces, const std::vector<int>& faces, Overlay& o) {
+  o.rb.clear();
+  o.cb.clear();
+  for (int i : faces) {
+    o.rb.push_back(pieces[i].pc.n0); o.rb.push_back(pieces[i].pc.n1);
+    o.cb.push_back(pieces[i].pc.m0); o.cb.push_back(pieces[i].pc.m1);
+  }
+  sorted_unique(o.rb);
+  sorted_unique(o.cb);
+  o.R = o.rb.size() - 1;
+  o.Cn = o.cb.size() - 1;
+  // each face's span of cells
+  std::vector<int32_t> span(4 * faces.size());
+  for (size_t f = 0; f < faces.size(); ++f) {
+    const Piece& p = pieces[faces[f]].pc;
+    span[4 * f + 0] = (int32_t)(std::lower_bound(o.rb.begin(), o.rb.end(), p.n0) - o.rb.begin());
+    span[4 * f + 1] = (int32_t)(std::lower_bound(o.rb.begin(), o.rb.end(), p.n1) - o.rb.begin());
+    span[4 * f + 2] = (int32_t)(std::lower_bound(o.cb.begin(), o.cb.end(), p.m0) - o.cb.begin());
+    span[4 * f + 3] = (int32_t)(std::lower_bound(o.cb.begin(), o.cb.end(), p.m1) - o.cb.begin());
+  }
+  o.start.assign(o.R * o.Cn + 1, 0);
+  for (size_t f = 0; f < faces.size(); ++f)
+    for (int32_t r = span[4 * f]; r < span[4 * f + 1]; ++r)
+      for (int32_t c = span[4 * f + 2]; c < span[4 * f + 3]; ++c) o.start[r * o.Cn + c + 1] += 1;
+  std::partial_sum(o.start.begin(), o.start.end(), o.start.begin());
+  o.list.resize(o.start.back());
+  std::vector<int32_t> pos(o.start.begin(), o.start.end() - 1);
+  for (size_t f = 0; f < faces.size(); ++f)
+    for (int32_t r = span[4 * f]; r < span[4 * f + 1]; ++r)
+      for (int32_t c = span[4 * f + 2]; c < span[4 * f + 3]; ++c) o.list[pos[r * o.Cn + c]++] = faces[f];
+  // fold order: faces covering one cell are disjoint in k, so their k0
+  // differ; the lists are short (one per k-cut above the cell)
+  for (size_t cell = 0; cell + 1 < o.start.size(); ++cell)
+    for (int32_t a = o.start[cell] + 1; a < o.start[cell + 1]; ++a) {
+      const int32_t x = o.list[a];
+      const int64_t kx = pieces[x].pc.k0;
+      int32_t b = a;
+      for (; b > o.start[cell] && pieces[o.list[b - 1]].pc.k0 > kx; --b) o.list[b] = o.list[b - 1];
+      o.list[b] = x;
+    }
+}
+
+}  // namespace
+
 HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_remap,
                     const std::vector<ProbGeom>& geom, int64_t temp_base, int red_vec, int fuse) {
+  (void)geom;
   HostPlan hp;
   hp.nwg = nwg;
   hp.xcd_remap = xcd_remap && nwg % 8 == 0;
 
-  // items grouped by workgroup, in piece order within a workgroup
-  std::vector<std::vector<int>> by_wg(nwg);
-  for (size_t i = 0; i < pieces.size(); ++i)
-    if (!pieces[i].pc.empty()) by_wg[pieces[i].wg].push_back((int)i);
-
   // temporary faces
   std::vector<int64_t> off(pieces.size(), -1);
   int64_t cur = temp_base;
+  int32_t nprob = 0;
   for (size_t i = 0; i < pieces.size(); ++i) {
     const Piece& p = pieces[i].pc;
     if (p.empty()) continue;
@@ -36,6 +113,7 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
     int64_t v = p.vol();
     hp.vmax = std::max(hp.vmax, v);
     hp.vmin = hp.n_pieces == 1 ? v : std::min(hp.vmin, v);
+    nprob = std::max(nprob, pieces[i].prob + 1);
     if (p.k0 > 0) {
       off[i] = cur;
       // faces start on 16-byte boundaries
@@ -45,24 +123,29 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
   }
   hp.temp_elems = cur - temp_base;
 
-  std::vector<int> item_piece;   // piece of each item
+  // items grouped by workgroup, in piece order within a workgroup
   hp.wg_off.assign(nwg + 1, 0);
-  for (int w = 0; w < nwg; ++w) {
-    hp.wg_off[w] = (int32_t)hp.items.size();
-    for (int i : by_wg[w]) {
-      item_piece.push_back(i);
+  for (size_t i = 0; i < pieces.size(); ++i)
+    if (!pieces[i].pc.empty()) hp.wg_off[pieces[i].wg + 1] += 1;
+  std::partial_sum(hp.wg_off.begin(), hp.wg_off.end(), hp.wg_off.begin());
+  std::vector<int> item_piece(hp.wg_off[nwg]);   // piece of each item
+  hp.items.resize(hp.wg_off[nwg]);
+  {
+    std::vector<int32_t> pos(hp.wg_off.begin(), hp.wg_off.end() - 1);
+    for (size_t i = 0; i < pieces.size(); ++i) {
       const Piece& p = pieces[i].pc;
-      WorkItem it;
+      if (p.empty()) continue;
+      const int32_t at = pos[pieces[i].wg]++;
+      item_piece[at] = (int)i;
+      WorkItem& it = hp.items[at];
       it.prob = pieces[i].prob;
       it.n0 = (int32_t)p.n0; it.n1 = (int32_t)p.n1;
       it.m0 = (int32_t)p.m0; it.m1 = (int32_t)p.m1;
       it.k0 = (int32_t)p.k0; it.k1 = (int32_t)p.k1;
       it.pad = 0;
       it.out_off = off[i];
-      hp.items.push_back(it);
     }
   }
-  hp.wg_off[nwg] = (int32_t)hp.items.size();
   if (hp.n_kcuts == 0) return hp;
   int vec = red_vec == 4 ? 4 : 1;
   for (size_t i = 0; i < pieces.size() && vec == 4; ++i) {
@@ -72,36 +155,22 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
   }
   hp.red_vec = vec;
 
-  // reduction cells per problem
-  std::map<int, std::vector<int>> temps_of;  // prob -> temp piece indices
+  // reduction cells per problem, problems in ascending order
+  std::vector<std::vector<int>> temps_of(nprob);
   for (size_t i = 0; i < pieces.size(); ++i)
     if (off[i] >= 0) temps_of[pieces[i].prob].push_back((int)i);
+  Overlay ov;
   if (fuse == 2) {   // fused unless some cell's fold is large
     fuse = 1;
-    for (auto& kv : temps_of) {
-      std::vector<int64_t> rb, cb;
-      for (int i : kv.second) {
-        rb.push_back(pieces[i].pc.n0); rb.push_back(pieces[i].pc.n1);
-        cb.push_back(pieces[i].pc.m0); cb.push_back(pieces[i].pc.m1);
-      }
-      std::sort(rb.begin(), rb.end()); rb.erase(std::unique(rb.begin(), rb.end()), rb.end());
-      std::sort(cb.begin(), cb.end()); cb.erase(std::unique(cb.begin(), cb.end()), cb.end());
-      const size_t Cn = cb.size() - 1;
-      std::vector<int64_t> nsrc((rb.size() - 1) * Cn, 0);
-      for (int i : kv.second) {
-        const Piece& p = pieces[i].pc;
-        size_t r0 = std::lower_bound(rb.begin(), rb.end(), p.n0) - rb.begin();
-        size_t r1 = std::lower_bound(rb.begin(), rb.end(), p.n1) - rb.begin();
-        size_t c0 = std::lower_bound(cb.begin(), cb.end(), p.m0) - cb.begin();
-        size_t c1 = std::lower_bound(cb.begin(), cb.end(), p.m1) - cb.begin();
-        for (size_t r = r0; r < r1; ++r)
-          for (size_t c = c0; c < c1; ++c) nsrc[r * Cn + c] += 1;
-      }
-      for (size_t r = 0; r + 1 < rb.size(); ++r)
-        for (size_t c = 0; c < Cn; ++c)
-          if (nsrc[r * Cn + c] > 0 &&
-              (rb[r + 1] - rb[r]) * (cb[c + 1] - cb[c]) * (nsrc[r * Cn + c] + 1) * 4 > kFuseCellBytes)
+    for (const std::vector<int>& tp : temps_of) {
+      if (tp.empty()) continue;
+      overlay(pieces, tp, ov);
+      for (size_t r = 0; r < ov.R; ++r)
+        for (size_t c = 0; c < ov.Cn; ++c) {
+          const int64_t ns = ov.start[r * ov.Cn + c + 1] - ov.start[r * ov.Cn + c];
+          if (ns > 0 && (ov.rb[r + 1] - ov.rb[r]) * (ov.cb[c + 1] - ov.cb[c]) * (ns + 1) * 4 > kFuseCellBytes)
             fuse = 0;
+        }
     }
   }
   hp.fused = fuse == 1;
@@ -109,35 +178,17 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
   hp.tiles.reserve((size_t)(hp.temp_elems / 1024) + 64);
   hp.srcs.reserve(4 * (size_t)hp.n_kcuts + 64);
   std::vector<std::vector<int32_t>> piece_cells(hp.fused ? pieces.size() : 0);
-  for (auto& kv : temps_of) {
-    const int prob = kv.first;
-    const std::vector<int>& tp = kv.second;
-    std::vector<int64_t> rb, cb;
-    for (int i : tp) {
-      rb.push_back(pieces[i].pc.n0); rb.push_back(pieces[i].pc.n1);
-      cb.push_back(pieces[i].pc.m0); cb.push_back(pieces[i].pc.m1);
-    }
-    std::sort(rb.begin(), rb.end()); rb.erase(std::unique(rb.begin(), rb.end()), rb.end());
-    std::sort(cb.begin(), cb.end()); cb.erase(std::unique(cb.begin(), cb.end()), cb.end());
-    const size_t R = rb.size() - 1, Cn = cb.size() - 1;
-    std::vector<std::vector<int>> cell(R * Cn);
-    for (int i : tp) {
-      const Piece& p = pieces[i].pc;
-      size_t r0 = std::lower_bound(rb.begin(), rb.end(), p.n0) - rb.begin();
-      size_t r1 = std::lower_bound(rb.begin(), rb.end(), p.n1) - rb.begin();
-      size_t c0 = std::lower_bound(cb.begin(), cb.end(), p.m0) - cb.begin();
-      size_t c1 = std::lower_bound(cb.begin(), cb.end(), p.m1) - cb.begin();
-      for (size_t r = r0; r < r1; ++r)
-        for (size_t c = c0; c < c1; ++c) cell[r * Cn + c].push_back(i);
-    }
-    for (size_t r = 0; r < R; ++r)
-      for (size_t c = 0; c < Cn; ++c) {
-        std::vector<int>& lst = cell[r * Cn + c];
-        if (lst.empty()) continue;
-        std::sort(lst.begin(), lst.end(),
-                  [&](int a, int b) { return pieces[a].pc.k0 < pieces[b].pc.k0; });
+  for (int32_t prob = 0; prob < nprob; ++prob) {
+    const std::vector<int>& tp = temps_of[prob];
+    if (tp.empty()) continue;
+    overlay(pieces, tp, ov);
+    for (size_t r = 0; r < ov.R; ++r)
+      for (size_t c = 0; c < ov.Cn; ++c) {
+        const int32_t l0 = ov.start[r * ov.Cn + c], l1 = ov.start[r * ov.Cn + c + 1];
+        if (l0 == l1) continue;
         int32_t s0 = (int32_t)hp.srcs.size();
-        for (int i : lst) {
+        for (int32_t l = l0; l < l1; ++l) {
+          const int i = ov.list[l];
           const Piece& p = pieces[i].pc;
           RedSrc s;
           s.off = off[i];
@@ -148,7 +199,7 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
           hp.srcs.push_back(s);
         }
         int32_t s1 = (int32_t)hp.srcs.size();
-        int64_t i0 = rb[r], i1 = rb[r + 1], j0 = cb[c], j1 = cb[c + 1];
+        int64_t i0 = ov.rb[r], i1 = ov.rb[r + 1], j0 = ov.cb[c], j1 = ov.cb[c + 1];
         if (hp.fused) {
           // one tile per cell; every piece of the problem meeting the cell
           // (its faces' pieces and the lowest-k ones writing C) counts
@@ -184,7 +235,6 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
             hp.tiles.push_back(t);
           }
       }
-    (void)geom;
   }
   if (hp.fused) {
     hp.item_fold.assign(2 * hp.items.size(), 0);

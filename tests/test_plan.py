@@ -290,3 +290,43 @@ def test_forced_ring_tile_plan(tile, prec, monkeypatch):
     A, B = workloads.small_int_operands(n, m, k, seed=tile)
     C, _ = replay("ring", A.astype(np.int64), B.astype(np.int64), n, m, k, p=64, precision=prec)
     np.testing.assert_array_equal(C, oracle.ring_i64(A.astype(np.int64), B.astype(np.int64)))
+
+
+@pytest.mark.parametrize("sr,n,m,k,kw", [
+    ("minplus", 384, 256, 320, dict(p=0)),
+    ("minplus", 384, 256, 320, dict(part="multi", p=200)),
+    ("ring", 2048, 1024, 65536, dict(p=256, precision="bf16x3")),
+    ("ring", 837, 837, 837, dict(p=256, precision="bf16x6")),
+    ("ring", 300, 200, 700, dict(part="multi", p=97)),
+    ("maxplus", 257, 513, 129, dict(p=251)),
+    ("minplus", 70, 50, 3000, dict(part="grid", p=37, split_k=5)),
+])
+def test_fold_sources_complete_and_in_k_order(sr, n, m, k, kw):
+    """Section "PACO MM" combines the temporary faces of height cuts by the
+    semiring's addition; for the float ring the order of that fold decides
+    the bits, and the plan fixes it as ascending k.  Every reduction tile
+    lists exactly the faces that cover it, each covering the whole tile,
+    in strictly ascending k0; every element covered by a face lies in
+    exactly one tile, and no tile lies outside the faces."""
+    items, _, tiles, srcs, info = P.plan_export(n, m, k, sr, **kw)
+    faces = {int(it[7]): it for it in items if it[7] >= 0}
+    assert len(faces) == sum(1 for it in items if it[7] >= 0) > 0   # distinct offsets
+    covered = np.zeros((n, m), np.int64)
+    for it in faces.values():
+        covered[it[1]:it[2], it[3]:it[4]] = 1
+    tiled = np.zeros((n, m), np.int64)
+    for t in tiles:
+        _, i0, i1, j0, j1, s0, s1 = (int(x) for x in t)
+        tiled[i0:i1, j0:j1] += 1
+        want = sorted((int(it[5]), off) for off, it in faces.items()
+                      if it[1] < i1 and it[2] > i0 and it[3] < j1 and it[4] > j0)
+        got = []
+        for s in range(s0, s1):
+            off, ld, r0, c0 = (int(x) for x in srcs[s])
+            it = faces[off]
+            assert (r0, c0, ld) == (it[1], it[3], it[4] - it[3])
+            assert it[1] <= i0 and i1 <= it[2] and it[3] <= j0 and j1 <= it[4], "face must cover its tile"
+            got.append((int(it[5]), off))
+        assert got == want, "sources must be every covering face, in ascending k"
+        assert all(a[0] < b[0] for a, b in zip(got, got[1:]))
+    np.testing.assert_array_equal(tiled, covered)
