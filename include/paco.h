@@ -48,7 +48,18 @@
 extern "C" {
 #endif
 
-typedef enum paco_status {
+/* The enumerations below are int32 in the ABI.  C++ callers and the library
+ * itself see them with that fixed underlying type, so that any int32 a C
+ * caller passes is a value the entry points can test and reject with
+ * PACO_ERR_INVALID_ARG (an out-of-range value of an enumeration without one
+ * is undefined in C++). */
+#ifdef __cplusplus
+#define PACO_ENUM_INT32 : int32_t
+#else
+#define PACO_ENUM_INT32
+#endif
+
+typedef enum paco_status PACO_ENUM_INT32 {
   PACO_OK = 0,
   PACO_ERR_INVALID_ARG = 1,   /* null pointer, negative size, bad enum, bad ld */
   PACO_ERR_UNSUPPORTED = 2,   /* e.g. Strassen on a non-ring semiring */
@@ -59,7 +70,7 @@ typedef enum paco_status {
   PACO_ERR_NOT_FOUND = 7      /* unknown server ticket */
 } paco_status;
 
-typedef enum paco_semiring {
+typedef enum paco_semiring PACO_ENUM_INT32 {
   PACO_SR_PLUS_TIMES_F32 = 0, /* (+,x) ring on float32 */
   PACO_SR_MIN_PLUS_I32 = 1,   /* tropical (min,+) on int32 */
   PACO_SR_MAX_PLUS_I32 = 2,   /* (max,+) on int32 */
@@ -79,7 +90,7 @@ typedef enum paco_semiring {
  *  AUTO   : BF16X3 when its predicted componentwise error at this k is at
  *           most 2^-21, BF16X6 otherwise.
  * Integer and boolean semirings ignore this field. */
-typedef enum paco_precision {
+typedef enum paco_precision PACO_ENUM_INT32 {
   PACO_PREC_FP32 = 0,
   PACO_PREC_BF16X3 = 1,
   PACO_PREC_BF16X6 = 2,
@@ -94,7 +105,7 @@ typedef enum paco_precision {
  *  GRID : the baseline the paper's experiments compare against in spirit:
  *         the same microkernel on a plain grid of output tiles with a
  *         split-k factor chosen by the autotuner. */
-typedef enum paco_part_mode {
+typedef enum paco_part_mode PACO_ENUM_INT32 {
   PACO_PART_PACO = 0,   /* MM-1-Piece: one piece per processor */
   PACO_PART_GRID = 1,   /* plain output-tile grid with split-k (baseline) */
   PACO_PART_MULTI = 2   /* multi-piece pruned BFS (theorem mm): every cut
@@ -265,7 +276,7 @@ paco_status paco_calibrate(paco_ctx ctx, int32_t p, int32_t iters, double* rates
  * workgroups per compute unit and is timed between events; it allocates
  * and frees its own buffers (2 GiB for the copy).  Synchronous.  Unknown
  * kind: PACO_ERR_INVALID_ARG. */
-typedef enum {
+typedef enum PACO_ENUM_INT32 {
   PACO_PEAK_MFMA_BF16 = 0,
   PACO_PEAK_VALU_I32 = 1,
   PACO_PEAK_VALU_F32 = 2,
@@ -362,7 +373,7 @@ paco_status paco_strassen_pbfs(paco_ctx ctx, const paco_strassen_desc* d, paco_s
  * INF), D[1..n] written.  Asynchronous on the context stream; the plan is
  * cached per (n, part, p, base, min_piece).  Calls on one context must not
  * overlap (each plan keeps its own launch counters). */
-typedef enum { PACO_W_AFFINE = 0, PACO_W_HASH = 1 } paco_w_kind;
+typedef enum PACO_ENUM_INT32 { PACO_W_AFFINE = 0, PACO_W_HASH = 1 } paco_w_kind;
 
 typedef struct paco_dp1d_desc {
   int64_t n;
