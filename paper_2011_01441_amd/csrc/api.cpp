@@ -503,7 +503,10 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
     // it crosses, so weighted ring cuts in n and m stay on tile multiples
     // (k cuts keep the 32-deep step)
     const bool wring = weights && fam == 2;
-    if (fam == 1) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
+    // integer cuts in m and k land on multiples of four, so the work items
+    // start 16-byte aligned for the kernel's 128-bit loads
+    if (fam == 0) { po.q[1] = 4; po.q[2] = 4; }
+    else if (fam == 1) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
     else if (fam == 2) { po.q[0] = wring ? 256 : 16; po.q[1] = wring ? 256 : 16; po.q[2] = 32; }
     auto part_for = [&](int pp) {
       po.p = pp;
@@ -1031,7 +1034,9 @@ paco_status paco::run_mm(paco_ctx ctx, const paco_mm_desc* d, paco_mm_result* re
   pr.base.lda = z.lda; pr.base.ldb = z.ldb; pr.base.ldc = z.ldc;
   pr.base.n = (int32_t)z.n; pr.base.m = (int32_t)z.m; pr.base.k = (int32_t)z.k;
   pr.base.accumulate = d->accumulate ? 1 : 0;
-  pr.vec_ok = ring_vec_ok(d->A, z.lda, d->B, z.ldb, z.m, z.k) ? 1 : 0;
+  // 128-bit operand loads: aligned rows of multiples of four elements, and
+  // for the integer kernel work items that start on such multiples
+  pr.vec_ok = ring_vec_ok(d->A, z.lda, d->B, z.ldb, z.m, z.k) && (dp->fam != 0 || dp->h.aligned4) ? 1 : 0;
   pr.stamps = ctx->stamps;
   pr.stamp_cap = ctx->stamps ? ctx->stamp_cap : 0;
   const int rvec = (dp->h.red_vec == 4 && (uintptr_t)d->C % 16 == 0 && z.ldc % 4 == 0) ? 4 : 1;

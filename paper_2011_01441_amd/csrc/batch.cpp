@@ -53,6 +53,7 @@ void split_rec(const std::vector<BatchReq>& reqs, const std::vector<int>& ids, s
       po.kcut_cost = default_kcut_cost(r.sr);
       const int g = batch_group(r);
       if (g == G_BOOL) { po.q[0] = 1; po.q[1] = 32; po.q[2] = 32; }
+      if (g == G_MINPLUS || g == G_MAXPLUS) { po.q[1] = 4; po.q[2] = 4; }   // 128-bit loads (as a call's plan)
       std::vector<Piece> pcs;
       if (g <= G_RING_X6 && tile >= 0) {
         int t = tile;

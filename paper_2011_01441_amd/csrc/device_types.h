@@ -37,8 +37,9 @@ struct ProbRef {
   Problem base;
   int64_t sA, sB, sC;  // element strides between consecutive problems
   int32_t vec_ok;      // set by the host: every problem's A and B rows are
-                       // 16-byte aligned with lengths multiple of 4 (the
-                       // ring kernel may use 128-bit loads)
+                       // 16-byte aligned with lengths multiple of 4, and
+                       // for the integer kernel every work item starts on
+                       // a multiple of 4 in k and m (128-bit loads)
   int32_t stamp_cap;   // processors with a slot in `stamps`
   uint64_t* stamps;    // null, or 4 words per processor: start and end of
                        // its work on the device's 100 MHz clock, its XCC_ID

@@ -6,7 +6,9 @@
 // 32.  A and B tiles are staged in LDS (A transposed so a thread reads RM/2
 // consecutive rows of one column with one vector read), double buffered with
 // one barrier per step; the next step's global loads are in flight while the
-// current one is computed.  Each thread owns an RM x RN register tile of
+// current one is computed.  Where the host finds every row and work item
+// 16-byte aligned (VEC), a thread fetches four consecutive elements of a row
+// with one 128-bit load; otherwise one element per 32-bit load.  Each thread owns an RM x RN register tile of
 // accumulators; consecutive pairs of l fold as min3/max3 (two adds and one
 // three-way min per two products).
 //
@@ -26,6 +28,8 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kBK = 32;
 constexpr int kLChunk = 8;
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct OpMin {
   using T = uint32_t;
@@ -52,7 +56,7 @@ struct OpMax {
   static __device__ __forceinline__ T finish(T v) { return v < kMaxPlusThreshold ? kMaxPlusNegInf : v; }
 };
 
-template <class Op, int TM, int TN, int RM, int RN>
+template <class Op, int TM, int TN, int RM, int RN, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_semiring_int(ProbRef pr, const WorkItem* __restrict__ items,
                                                             const int32_t* __restrict__ wg_off, int nwg,
                                                             int xcd, typename Op::T* __restrict__ ws) {
@@ -63,6 +67,10 @@ __global__ __launch_bounds__(kThreads) void k_semiring_int(ProbRef pr, const Wor
   constexpr int AP = TM + 4, BP = TN + 4;
   constexpr int HM = RM / 2, HN = RN / 2;
   constexpr int A_PER = kBK * TM / kThreads, B_PER = kBK * TN / kThreads;
+  // VEC: per step, A is TM rows of eight 4-element k-quads and B is kBK rows
+  // of TN / 4 column quads; each thread loads A_PER / 4 and B_PER / 4 quads
+  constexpr int A_PER4 = A_PER / 4, B_PER4 = B_PER / 4, BQ = TN / 4;
+  static_assert(!VEC || (A_PER % 4 == 0 && B_PER % 4 == 0 && kThreads % BQ == 0), "vector load split");
   __shared__ __align__(16) T As[2][kBK][AP];
   __shared__ __align__(16) T Bs[2][kBK][BP];
 
@@ -84,47 +92,84 @@ __global__ __launch_bounds__(kThreads) void k_semiring_int(ProbRef pr, const Wor
         for (int i = 0; i < RM; ++i)
 #pragma unroll
           for (int j = 0; j < RN; ++j) acc[i][j] = Op::acc0();
-        T ra[A_PER], rb[B_PER];
-        // Buffer loads: thread t reads A rows i0 + t/kBK + s*(kThreads/kBK) at
-        // column t % kBK of the step, and B rows kk + t/TN + s*(kThreads/TN)
-        // at column j0 + t % TN.  The per-s row offsets are uniform (scalar
-        // offsets); rows past the matrix read 0 through the buffer range
-        // check, rows past the piece are discarded, and the k-tail beyond
-        // the piece's k1 is replaced by the padding value.
-        constexpr int A_RSTEP = kThreads / kBK, B_RSTEP = kThreads / TN;
+        T ra[VEC ? 1 : A_PER], rb[VEC ? 1 : B_PER];
+        u32x4 ra4[VEC ? A_PER4 : 1], rb4[VEC ? B_PER4 : 1];
+        // Buffer loads.  32-bit: thread t reads A rows i0 + t/kBK +
+        // s*(kThreads/kBK) at column t % kBK of the step, and B rows kk + t/TN
+        // + s*(kThreads/TN) at column j0 + t % TN.  VEC: thread t reads A rows
+        // i0 + t/8 + s*(kThreads/8) at columns 4*(t % 8) .. +3 of the step, and
+        // B rows kk + t/BQ + s*(kThreads/BQ) at columns j0 + 4*(t % BQ) .. +3.
+        // The per-s row offsets are uniform (scalar offsets); rows past the
+        // matrix read 0 through the buffer range check, rows and columns past
+        // the piece are discarded, and the k-tail beyond the piece's k1 is
+        // replaced by the padding value.
+        constexpr int A_RSTEP = VEC ? kThreads / 8 : kThreads / kBK;
+        constexpr int B_RSTEP = VEC ? kThreads / BQ : kThreads / TN;
         const auto a_rsrc = make_rsrc(A + (int64_t)i0 * P.lda, P.n - i0, P.lda, P.k);
-        const int a_c = t % kBK;
-        int a_voff = ((t / kBK) * (int)P.lda + W.k0 + a_c) * 4;
+        const int a_c = VEC ? 4 * (t % 8) : t % kBK;   // first column of the step this thread loads
+        int a_voff = ((t / (kThreads / A_RSTEP)) * (int)P.lda + W.k0 + a_c) * 4;
         const int a_soff = A_RSTEP * (int)P.lda * 4;
-        const int b_voff = ((t / TN) * (int)P.ldb + j0 + t % TN) * 4;
+        const int b_c = VEC ? 4 * (t % BQ) : t % TN;
+        const int b_voff = ((t / (kThreads / B_RSTEP)) * (int)P.ldb + j0 + b_c) * 4;
         const int b_soff = B_RSTEP * (int)P.ldb * 4;
         // Loads only issue here; padding is applied when the registers are
         // written to LDS, so the loads stay in flight during the compute.
-        T a_pad = Op::nopad();
+        int a_lim = 0;    // columns of this thread's load still inside the piece
         int b_rows = 0;
         auto load = [&](int kk) {
-          a_pad = kk + a_c < W.k1 ? Op::nopad() : Op::pad();
+          a_lim = W.k1 - kk - a_c;
+          if constexpr (VEC) {
 #pragma unroll
-          for (int s = 0; s < A_PER; ++s)
-            ra[s] = (T)__builtin_amdgcn_raw_buffer_load_b32(a_rsrc, a_voff, s * a_soff, 0);
+            for (int s = 0; s < A_PER4; ++s)
+              ra4[s] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(a_rsrc, a_voff, s * a_soff, 0));
+          } else {
+#pragma unroll
+            for (int s = 0; s < A_PER; ++s)
+              ra[s] = (T)__builtin_amdgcn_raw_buffer_load_b32(a_rsrc, a_voff, s * a_soff, 0);
+          }
           a_voff += kBK * 4;
           const auto b_rsrc = make_rsrc(B + (int64_t)kk * P.ldb, P.k - kk, P.ldb, P.m);
-          b_rows = W.k1 - kk - t / TN;
+          b_rows = W.k1 - kk - t / (kThreads / B_RSTEP);
+          if constexpr (VEC) {
 #pragma unroll
-          for (int s = 0; s < B_PER; ++s)
-            rb[s] = (T)__builtin_amdgcn_raw_buffer_load_b32(b_rsrc, b_voff, s * b_soff, 0);
+            for (int s = 0; s < B_PER4; ++s)
+              rb4[s] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(b_rsrc, b_voff, s * b_soff, 0));
+          } else {
+#pragma unroll
+            for (int s = 0; s < B_PER; ++s)
+              rb[s] = (T)__builtin_amdgcn_raw_buffer_load_b32(b_rsrc, b_voff, s * b_soff, 0);
+          }
         };
         if (W.k0 < W.k1) load(W.k0);
         for (int kk = W.k0; kk < W.k1; kk += kBK) {
+          if constexpr (VEC) {
+            const int arow = t / 8;
 #pragma unroll
-          for (int s = 0; s < A_PER; ++s) {
-            int e = t + s * kThreads;
-            As[buf][e % kBK][e / kBK] = Op::pad_with(ra[s], a_pad);
-          }
+            for (int s = 0; s < A_PER4; ++s)
 #pragma unroll
-          for (int s = 0; s < B_PER; ++s) {
-            int e = t + s * kThreads;
-            Bs[buf][e / TN][e % TN] = Op::pad_with(rb[s], s * B_RSTEP < b_rows ? Op::nopad() : Op::pad());
+              for (int j = 0; j < 4; ++j)
+                As[buf][a_c + j][arow + s * A_RSTEP] =
+                    Op::pad_with((T)ra4[s][j], j < a_lim ? Op::nopad() : Op::pad());
+            const int brow = t / BQ;
+#pragma unroll
+            for (int s = 0; s < B_PER4; ++s) {
+              const T bp = s * B_RSTEP < b_rows ? Op::nopad() : Op::pad();
+              u32x4 v;
+#pragma unroll
+              for (int j = 0; j < 4; ++j) v[j] = (uint32_t)Op::pad_with((T)rb4[s][j], bp);
+              *(u32x4*)&Bs[buf][brow + s * B_RSTEP][b_c] = v;
+            }
+          } else {
+#pragma unroll
+            for (int s = 0; s < A_PER; ++s) {
+              int e = t + s * kThreads;
+              As[buf][e % kBK][e / kBK] = Op::pad_with(ra[s], 0 < a_lim ? Op::nopad() : Op::pad());
+            }
+#pragma unroll
+            for (int s = 0; s < B_PER; ++s) {
+              int e = t + s * kThreads;
+              Bs[buf][e / TN][e % TN] = Op::pad_with(rb[s], s * B_RSTEP < b_rows ? Op::nopad() : Op::pad());
+            }
           }
           __syncthreads();
           if (kk + kBK < W.k1) load(kk + kBK);
@@ -183,27 +228,30 @@ __global__ __launch_bounds__(kThreads) void k_semiring_int(ProbRef pr, const Wor
   stamp_end(pr, q);
 }
 
+template <class Op, int TM, int TN, int RM, int RN>
+void launch_shape(bool vec, dim3 g, dim3 b, hipStream_t s, const ProbRef& pr, const WorkItem* items,
+                  const int32_t* wg_off, int nwg, int xcd, typename Op::T* ws) {
+  if (vec)
+    hipLaunchKernelGGL((k_semiring_int<Op, TM, TN, RM, RN, true>), g, b, 0, s, pr, items, wg_off, nwg, xcd, ws);
+  else
+    hipLaunchKernelGGL((k_semiring_int<Op, TM, TN, RM, RN, false>), g, b, 0, s, pr, items, wg_off, nwg, xcd, ws);
+}
+
 template <class Op>
 hipError_t launch_op(int tile, const ProbRef& pr, const WorkItem* items, const int32_t* wg_off,
                      int nwg, int xcd, void* ws, hipStream_t s) {
   using T = typename Op::T;
   dim3 g(nwg), b(kThreads);
+  // 128-bit loads: the host sets vec_ok when every problem's A and B are
+  // 16-byte aligned with rows (and leading dimensions) of multiples of four
+  // elements and every work item starts on a multiple of four in k and m
+  const bool vec = pr.vec_ok != 0;
   switch (tile) {
-    case INT_T128x128:
-      hipLaunchKernelGGL((k_semiring_int<Op, 128, 128, 8, 8>), g, b, 0, s, pr, items, wg_off, nwg, xcd, (T*)ws);
-      break;
-    case INT_T256x64:
-      hipLaunchKernelGGL((k_semiring_int<Op, 256, 64, 8, 8>), g, b, 0, s, pr, items, wg_off, nwg, xcd, (T*)ws);
-      break;
-    case INT_T64x64:
-      hipLaunchKernelGGL((k_semiring_int<Op, 64, 64, 4, 4>), g, b, 0, s, pr, items, wg_off, nwg, xcd, (T*)ws);
-      break;
-    case INT_T64x128:
-      hipLaunchKernelGGL((k_semiring_int<Op, 64, 128, 4, 8>), g, b, 0, s, pr, items, wg_off, nwg, xcd, (T*)ws);
-      break;
-    case INT_T128x64:
-      hipLaunchKernelGGL((k_semiring_int<Op, 128, 64, 8, 4>), g, b, 0, s, pr, items, wg_off, nwg, xcd, (T*)ws);
-      break;
+    case INT_T128x128: launch_shape<Op, 128, 128, 8, 8>(vec, g, b, s, pr, items, wg_off, nwg, xcd, (T*)ws); break;
+    case INT_T256x64: launch_shape<Op, 256, 64, 8, 8>(vec, g, b, s, pr, items, wg_off, nwg, xcd, (T*)ws); break;
+    case INT_T64x64: launch_shape<Op, 64, 64, 4, 4>(vec, g, b, s, pr, items, wg_off, nwg, xcd, (T*)ws); break;
+    case INT_T64x128: launch_shape<Op, 64, 128, 4, 8>(vec, g, b, s, pr, items, wg_off, nwg, xcd, (T*)ws); break;
+    case INT_T128x64: launch_shape<Op, 128, 64, 8, 4>(vec, g, b, s, pr, items, wg_off, nwg, xcd, (T*)ws); break;
     default:
       return hipErrorInvalidValue;
   }
@@ -216,19 +264,19 @@ int occupancy_op(int tile) {
   hipError_t e = hipErrorInvalidValue;
   switch (tile) {
     case INT_T128x128:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 128, 128, 8, 8>, kThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 128, 128, 8, 8, true>, kThreads, 0);
       break;
     case INT_T256x64:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 256, 64, 8, 8>, kThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 256, 64, 8, 8, true>, kThreads, 0);
       break;
     case INT_T64x64:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 64, 64, 4, 4>, kThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 64, 64, 4, 4, true>, kThreads, 0);
       break;
     case INT_T64x128:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 64, 128, 4, 8>, kThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 64, 128, 4, 8, true>, kThreads, 0);
       break;
     case INT_T128x64:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 128, 64, 8, 4>, kThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_semiring_int<Op, 128, 64, 8, 4, true>, kThreads, 0);
       break;
   }
   return (e == hipSuccess && nb > 0) ? nb : 1;

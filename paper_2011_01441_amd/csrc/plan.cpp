@@ -114,6 +114,7 @@ HostPlan build_plan(const std::vector<TaggedPiece>& pieces, int nwg, bool xcd_re
     hp.vmax = std::max(hp.vmax, v);
     hp.vmin = hp.n_pieces == 1 ? v : std::min(hp.vmin, v);
     nprob = std::max(nprob, pieces[i].prob + 1);
+    if (p.k0 % 4 || p.m0 % 4) hp.aligned4 = false;
     if (p.k0 > 0) {
       off[i] = cur;
       // faces start on 16-byte boundaries

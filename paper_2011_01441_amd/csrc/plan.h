@@ -30,6 +30,9 @@ struct HostPlan {
   bool fused = false;
   std::vector<int32_t> item_fold;
   std::vector<int32_t> fold_list;
+  // every non-empty item starts on a multiple of four in k and m (the
+  // integer kernel's 128-bit loads need it)
+  bool aligned4 = true;
   // statistics over non-empty pieces
   int32_t n_pieces = 0, n_kcuts = 0;
   int64_t vmax = 0, vmin = 0;

@@ -235,16 +235,20 @@ paco_status launch_batch(paco_server s, Batch& b, std::vector<ReqState*>& rs, st
     const int nwg = bs.g1[g] - bs.g0[g];
     gp[g].h = build_plan(tp, nwg, false, geom, temp_base);
     temp_base += (gp[g].h.temp_elems + 63) / 64 * 64;
-    if (g <= G_RING_X6) {
-      gp[g].tile = bs.tile[g];
+    if (g != G_BOOL) {   // 128-bit operand loads (the boolean kernel has none)
       for (int i : gp[g].reqs) {
         const paco_request& q = rs[i]->r;
         if (!ring_vec_ok(q.A, q.lda ? q.lda : q.k, q.B, q.ldb ? q.ldb : q.m, q.m, q.k)) gp[g].vec = false;
       }
+    }
+    if (g <= G_RING_X6) {
+      gp[g].tile = bs.tile[g];
     } else if (g == G_BOOL) {
       gp[g].tile = choose_bool_tile(kpcs);
+      gp[g].vec = false;
     } else {
       gp[g].tile = choose_int_tile(kpcs);
+      if (!gp[g].h.aligned4) gp[g].vec = false;
     }
   }
   paco_status st = grow_ws(s, (uint64_t)temp_base * 4);
