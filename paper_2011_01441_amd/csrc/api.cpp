@@ -474,14 +474,13 @@ std::vector<Piece> ring_partition(int64_t n, int64_t m, int64_t k, int p, int pr
 // Relative time of f pieces per workgroup slot of a VALU plan: with one
 // piece per slot the slowest slot sets the end, with more the dispatcher
 // evens out the slots' speeds.
-static double slot_spread(int f) {
-  switch (f) {
-    case 1: return 1.2;
-    case 2: return 1.1;
-    case 4: return 1.045;
-    case 8: return 1.02;
-    default: return 1.0;
-  }
+// (f may be fractional: piece counts that are not a multiple of the slots)
+static double slot_spread(double f) {
+  if (f < 2) return 1.2;
+  if (f < 4) return 1.1;
+  if (f < 8) return 1.045;
+  if (f < 16) return 1.02;
+  return 1.0;
 }
 
 void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int split_k, int prec,
@@ -539,8 +538,13 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
       // These kernels stream about 8 elements per byte, so a k-cut also
       // costs L2 reuse (concurrent pieces no longer walk k in step); the
       // overhead term and the face traffic stand for that.
+      // relative time per padded element of each integer tile at its own
+      // occupancy, from full-size (min,+) 8192^3 and 4096^3 runs (64 x 64
+      // at four workgroups per CU = 0.95; 64 x 128 at three 2.5% faster,
+      // 128 x 64 at two 11% slower, 128 x 128 and 256 x 64 at one 28% and
+      // 36% slower)
       const int ci[5] = {INT_T128x128, INT_T256x64, INT_T64x128, INT_T64x64, INT_T128x64};
-      const double ei[5] = {1.0, 1.14, 1.05, 0.95, 1.0};
+      const double ei[5] = {1.22, 1.29, 0.926, 0.95, 1.06};
       const int cb[4] = {BOOL_T512x32W, BOOL_T128x128W, BOOL_T256x64W, BOOL_T64x64W};
       const double eb[4] = {1.0, 1.0, 0.98, 1.08};
       const int ncand = fam == 0 ? 5 : 4;
@@ -563,11 +567,19 @@ void make_mm_plan(int sr, int64_t n, int64_t m, int64_t k, int part, int p, int 
           occ = std::min(std::max(occ, 1), 8);
           const double tile_work = (double)tm_ * tn_ * 256;   // one tile, 256 deep
           const int slots = (occ > 1 && work >= (double)num_cus * occ * 4 * tile_work) ? num_cus * occ : num_cus;
-          for (int f : {1, 2, 4, 8, 16}) {
-            const int pt = slots * f;
+          // piece counts: one to sixteen per slot, and power-of-two multiples
+          // of the CUs (with three slots per CU those are the counts whose
+          // cuts of power-of-two sizes land on whole tiles)
+          std::vector<int> counts;
+          for (int f : {1, 2, 4, 8, 16}) counts.push_back(slots * f);
+          for (int j = 0; j <= 6; ++j)
+            if (std::find(counts.begin(), counts.end(), num_cus << j) == counts.end() && (num_cus << j) >= slots)
+              counts.push_back(num_cus << j);
+          for (int pt : counts) {
+            const double f = (double)pt / slots;
             // more pieces than slots only while each keeps a tile's worth of
             // work (the per-tile overhead term prices smaller ones)
-            if (f > 1 && work < (double)pt * tile_work) continue;
+            if (pt > slots && work < (double)pt * tile_work) continue;
             if (pt > 65536) continue;
             std::vector<Piece> v = part_for(pt);
             std::vector<double> load(pt, 0.0);   // per processor (multi-piece: several pieces)

@@ -286,6 +286,34 @@ def test_int_ragged_k_steps(ctx, tile, sr, monkeypatch):
         assert np.array_equal(host(ctx.semiring_mm(dev(A), dev(B), sr, p=5, kcut_cost=1.0)), ref), k
 
 
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("sr", ["minplus", "maxplus"])
+def test_int_vector_and_scalar_loads(ctx, tile, sr, monkeypatch):
+    """The integer kernel loads four elements at a time where rows and work
+    items are 16-byte aligned, one at a time otherwise.  The same operands
+    through the aligned path, through A one element off alignment, and
+    through a leading dimension that is not a multiple of four (B as well)
+    all give the oracle's result bit for bit, on every tile shape."""
+    monkeypatch.setenv("PACO_INT_TILE", str(tile))
+    n, m, k = 300, 260, 516
+    print(f"case: {sr} {n}x{m}x{k} tile {tile} aligned/offset/padded", flush=True)
+    gen = workloads.minplus_operands if sr == "minplus" else workloads.maxplus_operands
+    A, B = gen(n, m, k, seed=40 + tile)
+    ref = (oracle.minplus if sr == "minplus" else oracle.maxplus)(A, B)
+    dA, dB = dev(A), dev(B)
+    assert np.array_equal(host(ctx.semiring_mm(dA, dB, sr)), ref)
+    flat = torch.empty(n * k + 1, dtype=dA.dtype, device=DEV)
+    Aoff = flat[1:].view(n, k)
+    Aoff.copy_(dA)
+    assert Aoff.data_ptr() % 16 != 0
+    assert np.array_equal(host(ctx.semiring_mm(Aoff, dB, sr)), ref)
+    Apad = torch.empty(n, k + 1, dtype=dA.dtype, device=DEV)[:, :k]
+    Bpad = torch.empty(k, m + 3, dtype=dB.dtype, device=DEV)[:, :m]
+    Apad.copy_(dA)
+    Bpad.copy_(dB)
+    assert np.array_equal(host(ctx.semiring_mm(Apad, Bpad, sr)), ref)
+
+
 @pytest.mark.parametrize("tile", [0, 1, 2, 3])
 def test_bool_tiles_bit_exact(ctx, tile, monkeypatch):
     """Every boolean tile shape (4 x 16 register tiles on the three wide
