@@ -3,7 +3,6 @@ the pruned-BFS figure, exactly-p assignment per round, disjoint cover,
 balance for arbitrary (prime) p, the largest-piece volume of theorem mm, the
 MM-1-Piece dimension bound of its corollary, the heterogeneous ratio split,
 quanta and the k-cut cost option."""
-import itertools
 import json
 import math
 import os

@@ -3,7 +3,6 @@ Strassen" and corollary Strassen-Const-Pieces), pinned to the statements the
 paper makes about it rather than to the rule that generates it."""
 import math
 
-import numpy as np
 import pytest
 
 import paper_2011_01441_amd as P  # noqa: E402
