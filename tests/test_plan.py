@@ -330,3 +330,18 @@ def test_fold_sources_complete_and_in_k_order(sr, n, m, k, kw):
         assert got == want, "sources must be every covering face, in ascending k"
         assert all(a[0] < b[0] for a, b in zip(got, got[1:]))
     np.testing.assert_array_equal(tiled, covered)
+
+
+@pytest.mark.parametrize("sr", ["minplus", "maxplus"])
+@pytest.mark.parametrize("n,m,k,kw", [(384, 256, 320, dict(p=0)), (8192, 8192, 8192, dict(p=0)),
+                                      (3000, 3000, 3000, dict(p=0)), (300, 77, 129, dict(p=0)),
+                                      (1000, 999, 997, dict(p=251)), (97, 130, 75, dict(p=3)),
+                                      (384, 256, 320, dict(part="multi", p=200)),
+                                      (517, 260, 700, dict(part="grid", p=64, split_k=7))])
+def test_integer_items_start_four_aligned(sr, n, m, k, kw):
+    """The integer kernel's 128-bit loads need every work item to start on a
+    multiple of four in k and m (the call checks the operands' alignment);
+    integer plans cut m and k on multiples of four so that they all do."""
+    items, _, _, _, _ = P.plan_export(n, m, k, sr, **kw)
+    assert len(items) > 0
+    assert all(it[3] % 4 == 0 and it[5] % 4 == 0 for it in items)
