@@ -18,6 +18,8 @@
 // int32 with NEG_INF = -2^30 padding; any sum with a NEG_INF factor is below
 // -2^29 and any sum of finite entries (|x| <= 2^28) is at or above it, so
 // thresholding the final value at -2^29 reproduces the absorbing NEG_INF.
+#include <type_traits>
+
 #include "kcommon.h"
 #include "kernels.h"
 #include "kfold.h"
@@ -140,8 +142,12 @@ __global__ __launch_bounds__(kThreads) void k_semiring_int(ProbRef pr, const Wor
               rb[s] = (T)__builtin_amdgcn_raw_buffer_load_b32(b_rsrc, b_voff, s * b_soff, 0);
           }
         };
-        if (W.k0 < W.k1) load(W.k0);
-        for (int kk = W.k0; kk < W.k1; kk += kBK) {
+        // store_step(pad): the registers of one step into LDS buffer buf.
+        // Padding only changes values past the piece's k1, so it runs on a
+        // piece's last, partial step alone (a uniform branch); elsewhere
+        // pad_with(v, nopad()) would return v unchanged.
+        auto store_step = [&](auto pad_c) {
+          constexpr bool PAD = decltype(pad_c)::value;
           if constexpr (VEC) {
             const int arow = t / 8;
 #pragma unroll
@@ -149,28 +155,36 @@ __global__ __launch_bounds__(kThreads) void k_semiring_int(ProbRef pr, const Wor
 #pragma unroll
               for (int j = 0; j < 4; ++j)
                 As[buf][a_c + j][arow + s * A_RSTEP] =
-                    Op::pad_with((T)ra4[s][j], j < a_lim ? Op::nopad() : Op::pad());
+                    PAD ? Op::pad_with((T)ra4[s][j], j < a_lim ? Op::nopad() : Op::pad()) : (T)ra4[s][j];
             const int brow = t / BQ;
 #pragma unroll
             for (int s = 0; s < B_PER4; ++s) {
-              const T bp = s * B_RSTEP < b_rows ? Op::nopad() : Op::pad();
-              u32x4 v;
+              u32x4 v = rb4[s];
+              if constexpr (PAD) {
+                const T bp = s * B_RSTEP < b_rows ? Op::nopad() : Op::pad();
 #pragma unroll
-              for (int j = 0; j < 4; ++j) v[j] = (uint32_t)Op::pad_with((T)rb4[s][j], bp);
+                for (int j = 0; j < 4; ++j) v[j] = (uint32_t)Op::pad_with((T)rb4[s][j], bp);
+              }
               *(u32x4*)&Bs[buf][brow + s * B_RSTEP][b_c] = v;
             }
           } else {
 #pragma unroll
             for (int s = 0; s < A_PER; ++s) {
               int e = t + s * kThreads;
-              As[buf][e % kBK][e / kBK] = Op::pad_with(ra[s], 0 < a_lim ? Op::nopad() : Op::pad());
+              As[buf][e % kBK][e / kBK] = PAD ? Op::pad_with(ra[s], 0 < a_lim ? Op::nopad() : Op::pad()) : ra[s];
             }
 #pragma unroll
             for (int s = 0; s < B_PER; ++s) {
               int e = t + s * kThreads;
-              Bs[buf][e / TN][e % TN] = Op::pad_with(rb[s], s * B_RSTEP < b_rows ? Op::nopad() : Op::pad());
+              Bs[buf][e / TN][e % TN] =
+                  PAD ? Op::pad_with(rb[s], s * B_RSTEP < b_rows ? Op::nopad() : Op::pad()) : rb[s];
             }
           }
+        };
+        if (W.k0 < W.k1) load(W.k0);
+        for (int kk = W.k0; kk < W.k1; kk += kBK) {
+          if (W.k1 - kk < kBK) store_step(std::true_type{});
+          else store_step(std::false_type{});
           __syncthreads();
           if (kk + kBK < W.k1) load(kk + kBK);
           // chunks wholly past the piece's k-range hold only padding, whose
