@@ -366,19 +366,22 @@ def bench_server(torch, P, count, rate, check=32):
         C = cbuf[r["kind"]][o:o + r["n"] * r["m"]].view(r["n"], r["m"])
         views.append((a[:r["n"], :r["k"]], b[:r["k"], :r["m"]], C))
     ops = sum(2.0 * r["n"] * r["m"] * r["k"] for r in reqs)
-    out = {"requests": count, "rate_req_s": rate, "gop_total": ops / 1e9}
+    # the dispatcher polls 2 ms for the next request before it sleeps (a
+    # serving process with a core to spare; both modes use it)
+    spin = 0.002
+    out = {"requests": count, "rate_req_s": rate, "gop_total": ops / 1e9, "dispatcher_spin_s": spin}
     ctx = P.Context(0)
     for per_req in (False, True):
         mode = "per_request" if per_req else "batched"
         for load in ("open_loop", "saturation"):
-            srv = P.Server(ctx, per_request=per_req, hbm_budget=64 << 30)
+            srv = P.Server(ctx, per_request=per_req, hbm_budget=64 << 30, spin_s=spin)
             # warm the kernels once
             for i in range(3):
                 A_, B_, C_ = views[i]
                 srv.submit(A_, B_, C_, reqs[i]["kind"])
             srv.drain()
             srv.close()
-            srv = P.Server(ctx, per_request=per_req, hbm_budget=64 << 30)
+            srv = P.Server(ctx, per_request=per_req, hbm_budget=64 << 30, spin_s=spin)
             base = P.server_clock() + 0.02
             tickets = []
             for r, (A_, B_, C_) in zip(reqs, views):

@@ -58,6 +58,12 @@ typedef struct paco_server_opts {
   int32_t p;                    /* processors per batch (0 = compute units) */
   double batch_window_s;        /* after the first arrival, wait this long
                                    for more before launching (0 = none) */
+  double spin_s;                /* an idle dispatcher polls for new requests
+                                   (and completions) this long before it
+                                   sleeps; waking a sleeping thread costs
+                                   microseconds of scheduler latency.  For a
+                                   server with a CPU core to spare (0 = sleep
+                                   at once; negative: PACO_ERR_INVALID_ARG) */
 } paco_server_opts;
 
 typedef struct paco_server_stats {

@@ -161,7 +161,7 @@ class RequestResult(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_int32),
                 ("per_request", ctypes.c_int32), ("p", ctypes.c_int32),
-                ("batch_window_s", ctypes.c_double)]
+                ("batch_window_s", ctypes.c_double), ("spin_s", ctypes.c_double)]
 
 
 class ServerStats(ctypes.Structure):
@@ -742,9 +742,9 @@ def batch_partition(reqs, p):
 class Server:
     """Batching request server on a device (see include/paco_server.h)."""
 
-    def __init__(self, ctx, hbm_budget=0, max_batch=0, per_request=False, p=0, window_s=0.0):
+    def __init__(self, ctx, hbm_budget=0, max_batch=0, per_request=False, p=0, window_s=0.0, spin_s=0.0):
         self._L = lib()
-        o = ServerOpts(hbm_budget, max_batch, 1 if per_request else 0, p, window_s)
+        o = ServerOpts(hbm_budget, max_batch, 1 if per_request else 0, p, window_s, spin_s)
         h = ctypes.c_void_p()
         _check(self._L.paco_server_create(ctx._h, ctypes.byref(o), ctypes.byref(h)))
         self._h = h

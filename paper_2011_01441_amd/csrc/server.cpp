@@ -346,8 +346,19 @@ paco_status launch_batch(paco_server s, Batch& b, std::vector<ReqState*>& rs, st
 void dispatcher_main(paco_server s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
+  auto ready = [&] { return s->stop || (!s->queue.empty() && s->inflight.size() < 2); };
   while (true) {
-    s->cv.wait(lk, [&] { return s->stop || (!s->queue.empty() && s->inflight.size() < 2); });
+    if (!ready() && s->o.spin_s > 0) {
+      // poll before sleeping: a request arriving within spin_s is taken
+      // without the wake-up of a sleeping thread
+      const double until = paco_server_clock() + s->o.spin_s;
+      do {
+        lk.unlock();
+        std::this_thread::yield();
+        lk.lock();
+      } while (!ready() && paco_server_clock() < until);
+    }
+    s->cv.wait(lk, ready);
     if (s->stop && s->queue.empty()) break;
     if (s->o.batch_window_s > 0 && !s->o.per_request) {
       const double first = s->reqs[s->queue.front()].res.arrival_s;
@@ -459,7 +470,7 @@ extern "C" paco_status paco_server_create(paco_ctx ctx, const paco_server_opts* 
   if (opts) s->o = *opts;
   if (s->o.hbm_budget_bytes == 0) s->o.hbm_budget_bytes = 64ull << 30;
   if (s->o.max_batch <= 0) s->o.max_batch = 8192;
-  if (s->o.p < 0 || s->o.batch_window_s < 0) {
+  if (s->o.p < 0 || s->o.batch_window_s < 0 || !(s->o.spin_s >= 0)) {
     delete s;
     return PACO_ERR_INVALID_ARG;
   }

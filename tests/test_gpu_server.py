@@ -63,10 +63,10 @@ SHAPES = [("ring", 33, 47, 65), ("minplus", 100, 300, 50), ("ring", 640, 512, 70
           ("ring", 64, 64, 64), ("minplus", 77, 91, 700)] * 3
 
 
-@pytest.mark.parametrize("per_request", [False, True])
-def test_server_mixed_batch_matches_oracle(ctx, pools, per_request):
-    print(f"case: server per_request={per_request}", flush=True)
-    srv = P.Server(ctx, per_request=per_request)
+@pytest.mark.parametrize("per_request,spin_s", [(False, 0.0), (True, 0.0), (False, 0.002)])
+def test_server_mixed_batch_matches_oracle(ctx, pools, per_request, spin_s):
+    print(f"case: server per_request={per_request} spin_s={spin_s}", flush=True)
+    srv = P.Server(ctx, per_request=per_request, spin_s=spin_s)
     runs = _run(srv, pools, SHAPES)
     _check(pools, srv, runs)
     st = srv.stats()
@@ -169,3 +169,8 @@ def test_server_dispatch_paths(ctx, pools):
     st = srv.stats()
     assert st["batches"] == 1 and st["completed"] == 4, st
     srv.close()
+
+
+def test_server_rejects_negative_spin(ctx):
+    with pytest.raises(P.PacoError):
+        P.Server(ctx, spin_s=-1.0)
