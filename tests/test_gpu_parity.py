@@ -328,3 +328,47 @@ def test_bool_tiles_bit_exact(ctx, tile, monkeypatch):
             print(f"case: bool tile {tile} {n}x{m}x{k} {kw}", flush=True)
             got = host(ctx.semiring_mm(Ad, Bd, "bool", n=n, m=m, k=k, **kw)).view(np.uint32)
             assert np.array_equal(got, ref), kw
+
+
+@pytest.mark.parametrize("sr", ["ring", "minplus", "maxplus", "bool"])
+def test_degenerate_shapes(ctx, sr):
+    """Section "PACO MM" on empty cuboids: k = 0 is the empty fold, so C is
+    the semiring's zero (0, INF, NEG_INF, no bits set) as the oracle gives
+    it; with accumulate it leaves C unchanged; n = 0 or m = 0 writes
+    nothing.  Also rows of A and columns of B that are all zero elements
+    ((min,+): INF, (max,+): NEG_INF) give zero rows and columns of C."""
+    print(f"case: {sr} degenerate shapes", flush=True)
+    n, m = 37, 70
+    dt = torch.float32 if sr == "ring" else torch.int32
+    kw = dict(n=n, m=m, k=0) if sr == "bool" else {}
+    mw = (m + 31) // 32 if sr == "bool" else m
+    A0 = torch.empty((n, 0), dtype=dt, device=DEV)
+    B0 = torch.empty((0, mw), dtype=dt, device=DEV)
+    C = torch.full((n, mw), 5, dtype=dt, device=DEV)
+    ctx.semiring_mm(A0, B0, sr, C=C, **kw)
+    want = {"ring": 0, "minplus": oracle.INF, "maxplus": oracle.NEG_INF, "bool": 0}[sr]
+    assert (host(C) == want).all()
+    if sr == "minplus":
+        assert np.array_equal(host(C), oracle.minplus(np.zeros((n, 0), np.int32), np.zeros((0, m), np.int32)))
+    if sr == "maxplus":
+        assert np.array_equal(host(C), oracle.maxplus(np.zeros((n, 0), np.int32), np.zeros((0, m), np.int32)))
+    C.fill_(5)
+    ctx.semiring_mm(A0, B0, sr, C=C, accumulate=True, **kw)
+    assert (host(C) == 5).all()
+    # n = 0 and m = 0: valid calls that write nothing
+    k = 33
+    kw = dict(n=0, m=m, k=k) if sr == "bool" else {}
+    ctx.semiring_mm(torch.empty((0, (k + 31) // 32 if sr == "bool" else k), dtype=dt, device=DEV),
+                    torch.empty(((k if sr == "bool" else k), mw), dtype=dt, device=DEV), sr,
+                    C=torch.empty((0, mw), dtype=dt, device=DEV), **kw)
+    if sr in ("minplus", "maxplus"):
+        gen = workloads.minplus_operands if sr == "minplus" else workloads.maxplus_operands
+        A, B = gen(n, m, 300, seed=77)
+        zero = oracle.INF if sr == "minplus" else oracle.NEG_INF
+        A[3, :] = zero
+        A[:, 7] = zero
+        B[:, 11] = zero
+        got = host(ctx.semiring_mm(dev(A), dev(B), sr))
+        ref = (oracle.minplus if sr == "minplus" else oracle.maxplus)(A, B)
+        assert np.array_equal(got, ref)
+        assert (got[3, :] == zero).all() and (got[:, 11] == zero).all()
