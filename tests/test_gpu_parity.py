@@ -372,3 +372,30 @@ def test_degenerate_shapes(ctx, sr):
         ref = (oracle.minplus if sr == "minplus" else oracle.maxplus)(A, B)
         assert np.array_equal(got, ref)
         assert (got[3, :] == zero).all() and (got[:, 11] == zero).all()
+
+
+def _wide_range(shape, seed, stream):
+    """float32 sign x 2^e x [1, 2) with e uniform in [-40, 40]: entries
+    spanning 24 decades, from seeded counter-based words."""
+    w = workloads.words(seed, stream, 3 * int(np.prod(shape))).reshape(3, -1)
+    u = workloads.uniform01(w)
+    e = np.floor(u[0] * 81.0) - 40.0
+    sign = np.where(u[1] < 0.5, -1.0, 1.0)
+    return (sign * np.exp2(e) * (1.0 + u[2])).astype(np.float32).reshape(shape)
+
+
+@pytest.mark.parametrize("prec,bound", [("fp32", 2.0 ** -20), ("bf16x6", 2.0 ** -20), ("bf16x3", 2.0 ** -15)])
+def test_ring_wide_exponent_range(ctx, prec, bound):
+    """The split products on entries over 24 decades (no overflow, no
+    subnormal parts): bf16x6 and float32 stay within the 2^-20 componentwise
+    bound relative to |A||B|.  bf16x3 drops up to about 3 * 2^-18 |a||b| per
+    product (the lo*lo' term and the rounding of both low parts); its 2^-20
+    at long k relies on many terms of similar size averaging out, which a
+    wide range of exponents defeats, so here the bound is 2^-15 (emulated
+    with exact sums on these operands: 2^-15.9)."""
+    n, m, k = 200, 130, 777
+    print(f"case: ring wide range {prec}", flush=True)
+    A, B = _wide_range((n, k), 3, 90), _wide_range((k, m), 3, 91)
+    C = host(ctx.semiring_mm(dev(A), dev(B), "ring", precision=prec))
+    assert np.isfinite(C).all()
+    assert comp_err(C, A.astype(np.float64), B.astype(np.float64)) <= bound
