@@ -88,7 +88,11 @@ typedef enum paco_semiring PACO_ENUM_INT32 {
  *           combined significance reaches float32 (hi*hi', hi*mid',
  *           mid*hi', mid*mid', hi*lo', lo*hi').
  *  AUTO   : BF16X3 when its predicted componentwise error at this k is at
- *           most 2^-21, BF16X6 otherwise.
+ *           most 2^-21, BF16X6 otherwise.  The prediction is for entries of
+ *           similar magnitude (errors of many terms averaging out); where a
+ *           few large terms dominate each output, as with entries spread
+ *           over many decades, BF16X3 can reach about 2^-15 and BF16X6
+ *           should be asked for explicitly.
  * Integer and boolean semirings ignore this field. */
 typedef enum paco_precision PACO_ENUM_INT32 {
   PACO_PREC_FP32 = 0,
