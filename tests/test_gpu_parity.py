@@ -399,3 +399,49 @@ def test_ring_wide_exponent_range(ctx, prec, bound):
     C = host(ctx.semiring_mm(dev(A), dev(B), "ring", precision=prec))
     assert np.isfinite(C).all()
     assert comp_err(C, A.astype(np.float64), B.astype(np.float64)) <= bound
+
+
+@pytest.mark.parametrize("sr", ["minplus", "maxplus"])
+def test_int_domain_edges(ctx, sr):
+    """Entries at the ends of the integer domains: (min,+) values up to
+    INF = 2^30, whose sums reach 2^31 and saturate to INF; (max,+) values
+    at -2^28 and 2^28 beside NEG_INF, so finite sums sit right at the
+    threshold that tells them from absorbed ones.  Bit-exact against the
+    oracle."""
+    n, m, k = 130, 97, 211
+    print(f"case: {sr} domain edges", flush=True)
+    w = workloads.words(9, 95 if sr == "minplus" else 96, 2 * (n * k + k * m)).reshape(2, -1)
+    u = workloads.uniform01(w)
+    if sr == "minplus":
+        # half the entries within 2^10 of INF, a tenth exactly INF, the rest small
+        def mk(a, b):
+            v = np.where(u[0, a:b] < 0.5, (1 << 30) - np.floor(u[1, a:b] * 1024.0),
+                         np.floor(u[1, a:b] * 1000.0))
+            return np.where(u[0, a:b] > 0.9, float(oracle.INF), v).astype(np.int64).astype(np.int32)
+        fn = oracle.minplus
+    else:
+        lim = oracle.MAXPLUS_FINITE_MAX
+        def mk(a, b):
+            v = np.where(u[0, a:b] < 0.45, -lim, np.where(u[0, a:b] < 0.9, lim, oracle.NEG_INF))
+            v = np.where(u[1, a:b] < 0.2, np.floor(u[1, a:b] * 2000.0) - 1000.0, v)
+            return v.astype(np.int64).astype(np.int32)
+        fn = oracle.maxplus
+    A = mk(0, n * k).reshape(n, k)
+    B = mk(n * k, n * k + k * m).reshape(k, m)
+    # rows of A and columns of B that put the outputs on the edges
+    if sr == "minplus":
+        A[0::3, :] = np.maximum(A[0::3, :], (1 << 30) - 1024)   # with the columns below: INF
+        A[1::3, :] = np.maximum(A[1::3, :], (1 << 29) - 7)
+        B[:, 1::3] = np.maximum(B[:, 1::3], (1 << 29) + 3)      # (1::3, 1::3): sums just below INF
+    else:
+        A[0::3, :] = -lim
+        B[:, 0::3] = -lim                                       # (0::3, 0::3): exactly -2^29
+        A[1::3, 1:] = oracle.NEG_INF                            # one finite column left
+        B[0, 2::3] = oracle.NEG_INF
+    ref = fn(A, B)
+    if sr == "minplus":
+        assert (ref[0::3, 1::3] == oracle.INF).all() and (ref[1::3, 1::3] < oracle.INF).any()
+    else:
+        assert (ref[0::3, 0::3] == -2 * lim).all() and (ref == oracle.NEG_INF).any()
+    assert np.array_equal(host(ctx.semiring_mm(dev(A), dev(B), sr)), ref)
+    assert np.array_equal(host(ctx.semiring_mm(dev(A), dev(B), sr, part="grid", split_k=3)), ref)
