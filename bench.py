@@ -503,7 +503,8 @@ def config_summary(torch, P, ctx, label, name, steps):
            "roofline": {"kernel": {"strassen": "k_ring", "minplus": "k_semiring_int", "maxplus": "k_semiring_int",
                                    "bool": "k_semiring_bool"}[w["kind"]],
                         "bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
-                        "frac": round(achieved / peak, 4), "kernel_ms": round(kern_ms, 4),
+                        "frac": round(achieved / peak, 4), "traffic": measured_traffic(name),
+                        "kernel_ms": round(kern_ms, 4),
                         "kernel_launches_per_step": round(tm["launches"] / steps, 2),
                         "reduce_ms": round(tm["reduce_ms"] / steps, 4),
                         "other_ms": round(tm["other_ms"] / steps, 4)}}
