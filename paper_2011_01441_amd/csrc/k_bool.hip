@@ -8,7 +8,7 @@
 // row and bit, shared by all of the thread's C words) every (row, bit, word)
 // step is a single and-or (a thread's 4 x 16 register tile: one extract per
 // sixteen and-ors).  A cuboid's C face is swept in TM-row by TNW-word
-// tiles; its k-range (bits, cut on multiples of 32) is folded 64 bits per
+// tiles; its k-range (bits, cut on multiples of 32) is folded 128 bits per
 // step through double-buffered LDS.
 #include "kcommon.h"
 #include "kernels.h"
@@ -18,7 +18,7 @@ namespace paco {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kBKB = 64;            // bits per step
+constexpr int kBKB = 128;           // bits per step
 constexpr int kKW = kBKB / 32;      // A words per row per step
 
 // All ones if bit l of w is set, else 0 (sign-extended one-bit field,
