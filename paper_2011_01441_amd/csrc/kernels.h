@@ -23,7 +23,7 @@ hipError_t launch_semiring_int(int sr, int tile, const ProbRef& pr, const WorkIt
                                hipStream_t s);
 
 // Boolean OR-AND kernel on bit-packed words.
-// Tile shapes of the boolean kernel: TM rows x TNW words, 64 bits per step.
+// Tile shapes of the boolean kernel: TM rows x TNW words, 128 bits per step.
 enum BoolTile : int { BOOL_T512x32W = 0, BOOL_T128x128W = 1, BOOL_T256x64W = 2, BOOL_T64x64W = 3 };
 struct BoolTileShape { int tm, tnw; };
 BoolTileShape bool_tile_shape(int tile);
